@@ -1,0 +1,113 @@
+/*
+ * trbt.h -- tridiagonal-to-banded eigenvector back-transformation on AMD
+ * Instinct MI355X (gfx950).
+ *
+ * The operation (Yu et al., "GPU-Acceleration of the ELPA2 Distributed
+ * Eigensolver for Dense Symmetric and Hermitian Eigenproblems", Sec. 2.2.2,
+ * Eq. 2stage_bkwd1 and Eq. kernel):
+ *
+ *     Y = Q^* X,   Q^* = H_0 H_1 ... H_{K-1},   H_k = I - tau_k v_k v_k^H,
+ *
+ * i.e. every Householder reflector produced by the banded-to-tridiagonal
+ * bulge chasing (Sec. 2.2.1, Eq. householder) is applied to every column of
+ * the eigenvector matrix in exactly the reverse of its generation order:
+ *
+ *     for k = K-1 down to 0:   z[r0_k : r0_k+len_k] -= tau_k v_k (v_k^H z[...])
+ *
+ * Reflector geometry (0-based; the paper's stage i = s+1, sweep j+1):
+ *   stages s = 0 .. n-3; stage s has S_s = ceil((n-s-2)/nbw) sweeps (slots)
+ *   (none when nbw = 1, where the band is already tridiagonal);
+ *   reflector (s, j) acts on rows [r0, r0+len) with r0 = s+1+j*nbw,
+ *   len = min(nbw, n-r0) >= 2; generation order is stage-major, slot-minor,
+ *   so reflector (s, j) has index k = S_0 + ... + S_{s-1} + j.
+ *
+ * Data layout:
+ *   hh_v    K x nbw, reflector-contiguous (reflector k at hh_v + k*nbw), in
+ *           generation order.  v[0] is read, not assumed to be 1.  Entries
+ *           at positions >= len_k are ignored.
+ *   hh_tau  K scalars.
+ *   Z       n x nev, column-major (LAPACK/ELPA convention), leading
+ *           dimension ldz >= max(1, n).  Overwritten in place with Y.
+ *           Rows n .. ldz-1 are never read or written.
+ *
+ * All data pointers are DEVICE pointers.  The caller owns every buffer.
+ * Calls are asynchronous on the given HIP stream (pass the hipStream_t as
+ * void*; NULL means the default stream), reentrant, and keep no state
+ * between calls.  No entry point below allocates device memory or
+ * synchronizes the device.  Kernel-time faults surface at the caller's next
+ * synchronization, not as a return code.
+ *
+ * Return codes: TRBT_SUCCESS (0); -i when argument i (1-based) is invalid,
+ * checked on the host before anything is launched; or one of the
+ * TRBT_ERR_* codes below.  No C++ exception crosses this interface.
+ */
+#ifndef TRBT_H
+#define TRBT_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define TRBT_SUCCESS 0
+#define TRBT_ERR_DEVICE (-100)    /* current device is not gfx950          */
+#define TRBT_ERR_WORKSPACE (-101) /* work too small or misaligned          */
+#define TRBT_ERR_HIP (-102)       /* a HIP runtime call / launch failed    */
+#define TRBT_ERR_INTERNAL (-103)  /* unexpected state (should not happen)  */
+
+#define TRBT_NBW_MAX 256          /* largest semi-bandwidth accepted       */
+#define TRBT_WORK_ALIGN 256       /* required alignment of `work`, bytes   */
+
+/* Complex FP64 element: layout-compatible with hipDoubleComplex and with
+ * torch.complex128 / numpy complex128. */
+typedef struct {
+    double re, im;
+} trbt_z;
+
+/* Host-only helpers, pure functions (no HIP calls).
+ * trbt_num_reflectors: K for (n, nbw); 0 when n < 3 or nbw == 1.
+ * trbt_stage_offsets:  off[s] = generation index of reflector (s, 0) for
+ *                      s = 0..n-2 (off[n-2] = K); needs n >= 2.
+ * Errors: -1 (n < 0), -2 (nbw outside [1, TRBT_NBW_MAX]), -3 (null out). */
+int trbt_num_reflectors(int64_t n, int nbw, int64_t *K);
+int trbt_stage_offsets(int64_t n, int nbw, int64_t *off);
+
+/* Bytes of device workspace the back-transformation of (n, nbw, nev) needs
+ * (real: is_complex = 0, complex: 1).  The workspace holds the per-block
+ * compact-WY factors the blocked kernels precompute; it may be 0 for shapes
+ * served by the unblocked kernel.  The same workspace can be reused by any
+ * later call with the same or smaller sizes.  Errors as for the transform
+ * (-1 n, -2 nbw, -3 nev; -4 null `bytes`). */
+int trbt_workspace_bytes(int64_t n, int nbw, int64_t nev, int is_complex, size_t *bytes);
+
+/* Y = Q^* X in place (Eq. 2stage_bkwd1), real FP64.
+ * Arguments: 1 n >= 0, 2 nbw in [1, TRBT_NBW_MAX], 3 0 <= nev <= n,
+ * 4 hh_v, 5 hh_tau (non-null unless K == 0 or nev == 0), 6 Z (non-null
+ * unless nev == 0 or n == 0), 7 ldz >= max(1, n), 8 work (device, aligned
+ * to TRBT_WORK_ALIGN; may be NULL when 9 work_bytes is 0 and
+ * trbt_workspace_bytes reports 0), 9 work_bytes, 10 stream.
+ * The contents of `work` on entry do not matter; on exit they are
+ * unspecified.  n < 3, nbw == 1 or nev == 0 return TRBT_SUCCESS without
+ * touching Z. */
+int trans_ev_tridi_to_band_d(int64_t n, int nbw, int64_t nev,
+                             const double *hh_v, const double *hh_tau,
+                             double *Z, int64_t ldz,
+                             void *work, size_t work_bytes, void *stream);
+
+/* Complex FP64 (Hermitian problems); tau is complex as produced by the
+ * standard complex Householder method.  Same contract as the real call. */
+int trans_ev_tridi_to_band_z(int64_t n, int nbw, int64_t nev,
+                             const trbt_z *hh_v, const trbt_z *hh_tau,
+                             trbt_z *Z, int64_t ldz,
+                             void *work, size_t work_bytes, void *stream);
+
+/* Static description of a status code (never NULL). */
+const char *trbt_strerror(int status);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* TRBT_H */

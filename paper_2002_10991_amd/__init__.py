@@ -1,0 +1,151 @@
+"""Python binding for libtrbt.so: the MI355X tridiagonal-to-banded eigenvector
+back-transformation (Yu et al., CPC 2020, Sec. 2.2.2, Eq. 2stage_bkwd1).
+
+Argument marshalling only: every step of the computation runs in the HIP
+kernels of ``csrc/trbt.hip`` behind the C ABI declared in ``include/trbt.h``.
+PyTorch supplies device memory and the stream.  There is no CPU fallback: if
+the library is missing, every call raises.
+
+The functions carry the C names.  Device buffers are passed as torch tensors
+(their data_ptr is taken) or as raw integer addresses.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+
+__all__ = [
+    "TrbtError", "lib", "trbt_num_reflectors", "trbt_stage_offsets", "trbt_workspace_bytes",
+    "trans_ev_tridi_to_band_d", "trans_ev_tridi_to_band_z", "trbt_strerror", "back_transform",
+    "TRBT_WORK_ALIGN", "TRBT_NBW_MAX",
+]
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libtrbt.so")
+TRBT_WORK_ALIGN = 256
+TRBT_NBW_MAX = 256
+_lib = None
+
+
+class TrbtError(RuntimeError):
+    def __init__(self, status: int, where: str):
+        self.status = status
+        super().__init__(f"{where}: status {status} ({trbt_strerror(status)})")
+
+
+def lib():
+    """Load libtrbt.so (built by ``python -m paper_2002_10991_amd.build``)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"{LIB_PATH} is not built; run python -m paper_2002_10991_amd.build")
+        L = C.CDLL(LIB_PATH)
+        i64, i32, vp, sz = C.c_int64, C.c_int, C.c_void_p, C.c_size_t
+        L.trbt_num_reflectors.argtypes = [i64, i32, C.POINTER(i64)]
+        L.trbt_stage_offsets.argtypes = [i64, i32, C.POINTER(i64)]
+        L.trbt_workspace_bytes.argtypes = [i64, i32, i64, i32, C.POINTER(sz)]
+        for f in (L.trans_ev_tridi_to_band_d, L.trans_ev_tridi_to_band_z):
+            f.argtypes = [i64, i32, i64, vp, vp, vp, i64, vp, sz, vp]
+            f.restype = i32
+        L.trbt_strerror.argtypes = [i32]
+        L.trbt_strerror.restype = C.c_char_p
+        _lib = L
+    return _lib
+
+
+def _ptr(x) -> int | None:
+    if x is None:
+        return None
+    if isinstance(x, int):
+        return x
+    return int(x.data_ptr())
+
+
+def _stream(stream) -> int | None:
+    if stream is None:
+        import torch
+        return int(torch.cuda.current_stream().cuda_stream)
+    if isinstance(stream, int):
+        return stream
+    return int(stream.cuda_stream)
+
+
+def trbt_strerror(status: int) -> str:
+    return lib().trbt_strerror(int(status)).decode()
+
+
+def trbt_num_reflectors(n: int, nbw: int) -> int:
+    K = C.c_int64()
+    rc = lib().trbt_num_reflectors(n, nbw, C.byref(K))
+    if rc:
+        raise TrbtError(rc, "trbt_num_reflectors")
+    return K.value
+
+
+def trbt_stage_offsets(n: int, nbw: int) -> np.ndarray:
+    off = np.zeros(max(n - 1, 1), np.int64)
+    rc = lib().trbt_stage_offsets(n, nbw, off.ctypes.data_as(C.POINTER(C.c_int64)))
+    if rc:
+        raise TrbtError(rc, "trbt_stage_offsets")
+    return off
+
+
+def trbt_workspace_bytes(n: int, nbw: int, nev: int, is_complex: bool) -> int:
+    b = C.c_size_t()
+    rc = lib().trbt_workspace_bytes(n, nbw, nev, int(bool(is_complex)), C.byref(b))
+    if rc:
+        raise TrbtError(rc, "trbt_workspace_bytes")
+    return b.value
+
+
+def trans_ev_tridi_to_band_d(n, nbw, nev, hh_v, hh_tau, Z, ldz, work, work_bytes, stream=None) -> int:
+    """Status-returning call of the C entry point (real FP64)."""
+    return lib().trans_ev_tridi_to_band_d(n, nbw, nev, _ptr(hh_v), _ptr(hh_tau), _ptr(Z), ldz,
+                                          _ptr(work), work_bytes, _stream(stream))
+
+
+def trans_ev_tridi_to_band_z(n, nbw, nev, hh_v, hh_tau, Z, ldz, work, work_bytes, stream=None) -> int:
+    """Status-returning call of the C entry point (complex FP64)."""
+    return lib().trans_ev_tridi_to_band_z(n, nbw, nev, _ptr(hh_v), _ptr(hh_tau), _ptr(Z), ldz,
+                                          _ptr(work), work_bytes, _stream(stream))
+
+
+def alloc_workspace(n: int, nbw: int, nev: int, is_complex: bool, device="cuda"):
+    """A torch uint8 device buffer of the size the call needs (or None)."""
+    import torch
+    nb = trbt_workspace_bytes(n, nbw, nev, is_complex)
+    if nb == 0:
+        return None
+    buf = torch.empty(nb + TRBT_WORK_ALIGN, dtype=torch.uint8, device=device)
+    off = (-buf.data_ptr()) % TRBT_WORK_ALIGN
+    return buf[off: off + nb]
+
+
+def back_transform(Z, hh_v, hh_tau, nbw: int, work=None, stream=None):
+    """In-place Y = Q^* X on a CUDA/HIP tensor.
+
+    Z: (n, nev) float64 or complex128 tensor with unit row stride (a
+    column-major view, e.g. ``buf.T[:n]`` of a (nev, ldz) buffer).
+    hh_v: (K, nbw) contiguous, hh_tau: (K,) contiguous, same dtype family.
+    Returns Z."""
+    import torch
+    n, nev = Z.shape
+    if nev and n and Z.stride(0) != 1:
+        raise ValueError("Z must be column-major (unit row stride)")
+    ldz = Z.stride(1) if nev > 1 else max(n, 1)
+    cplx = Z.dtype == torch.complex128
+    if not cplx and Z.dtype != torch.float64:
+        raise TypeError("Z must be float64 or complex128")
+    for name, t in (("hh_v", hh_v), ("hh_tau", hh_tau)):
+        if t.dtype != Z.dtype or not t.is_contiguous():
+            raise TypeError(f"{name} must be contiguous and of Z's dtype")
+    if work is None:
+        work = alloc_workspace(n, nbw, nev, cplx, Z.device)
+    wb = 0 if work is None else work.numel() * work.element_size()
+    f = trans_ev_tridi_to_band_z if cplx else trans_ev_tridi_to_band_d
+    rc = f(n, nbw, nev, hh_v, hh_tau, Z, max(ldz, 1), work, wb, stream)
+    if rc:
+        raise TrbtError(rc, f.__name__)
+    return Z
