@@ -103,6 +103,27 @@ int trans_ev_tridi_to_band_z(int64_t n, int nbw, int64_t nev,
                              trbt_z *Z, int64_t ldz,
                              void *work, size_t work_bytes, void *stream);
 
+/* The same operation in two steps, for callers that time or reuse them:
+ *   trbt_prepare_*  precomputes, from hh_v/hh_tau only, the per-block
+ *                   compact-WY factors into `work` (arguments as above:
+ *                   1 n, 2 nbw, 3 hh_v, 4 hh_tau, 5 work, 6 work_bytes,
+ *                   7 stream; work_bytes must be at least
+ *                   trbt_workspace_bytes(n, nbw, n, is_complex));
+ *   trbt_apply_*    applies them to Z (arguments exactly as for
+ *                   trans_ev_tridi_to_band_*).
+ * apply must follow a prepare of the same (n, nbw, hh_v, hh_tau contents)
+ * on the same workspace, ordered on the stream; one prepare can serve any
+ * number of applies to different Z (the factors depend on the reflectors
+ * only).  trans_ev_tridi_to_band_* is exactly prepare followed by apply. */
+int trbt_prepare_d(int64_t n, int nbw, const double *hh_v, const double *hh_tau,
+                   void *work, size_t work_bytes, void *stream);
+int trbt_prepare_z(int64_t n, int nbw, const trbt_z *hh_v, const trbt_z *hh_tau,
+                   void *work, size_t work_bytes, void *stream);
+int trbt_apply_d(int64_t n, int nbw, int64_t nev, const double *hh_v, const double *hh_tau,
+                 double *Z, int64_t ldz, void *work, size_t work_bytes, void *stream);
+int trbt_apply_z(int64_t n, int nbw, int64_t nev, const trbt_z *hh_v, const trbt_z *hh_tau,
+                 trbt_z *Z, int64_t ldz, void *work, size_t work_bytes, void *stream);
+
 /* Static description of a status code (never NULL). */
 const char *trbt_strerror(int status);
 

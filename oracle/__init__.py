@@ -60,6 +60,7 @@ def lib():
                                     C.c_void_p, _i64]
         L.orc_tridi_ql.argtypes = [_i64, _dp, _dp, _dp, _i64]
         L.orc_jacobi_d.argtypes = [_i64, _dp, _dp, _dp]
+        L.orc_num_threads.restype = C.c_int
         _lib = L
     return _lib
 
@@ -75,6 +76,11 @@ def _v(a: np.ndarray):
 def _check(rc: int, what: str):
     if rc != 0:
         raise RuntimeError(f"oracle {what} failed with status {rc}")
+
+
+def num_threads() -> int:
+    """OpenMP threads the oracle's parallel loops use."""
+    return int(lib().orc_num_threads())
 
 
 # --------------------------------------------------------------------------

@@ -34,8 +34,12 @@
 #include <stdint.h>
 #include <stdlib.h>
 #include <string.h>
+#include <omp.h>
 
 typedef double complex zc;
+
+/* threads the OpenMP loops below use */
+int orc_num_threads(void) { return omp_get_max_threads(); }
 
 #define ORC_OK 0
 #define ORC_EARG (-1)

@@ -18,7 +18,8 @@ import numpy as np
 
 __all__ = [
     "TrbtError", "lib", "trbt_num_reflectors", "trbt_stage_offsets", "trbt_workspace_bytes",
-    "trans_ev_tridi_to_band_d", "trans_ev_tridi_to_band_z", "trbt_strerror", "back_transform",
+    "trans_ev_tridi_to_band_d", "trans_ev_tridi_to_band_z", "trbt_prepare_d", "trbt_prepare_z",
+    "trbt_apply_d", "trbt_apply_z", "trbt_strerror", "back_transform", "alloc_workspace",
     "TRBT_WORK_ALIGN", "TRBT_NBW_MAX",
 ]
 
@@ -46,8 +47,12 @@ def lib():
         L.trbt_num_reflectors.argtypes = [i64, i32, C.POINTER(i64)]
         L.trbt_stage_offsets.argtypes = [i64, i32, C.POINTER(i64)]
         L.trbt_workspace_bytes.argtypes = [i64, i32, i64, i32, C.POINTER(sz)]
-        for f in (L.trans_ev_tridi_to_band_d, L.trans_ev_tridi_to_band_z):
+        for f in (L.trans_ev_tridi_to_band_d, L.trans_ev_tridi_to_band_z, L.trbt_apply_d,
+                  L.trbt_apply_z):
             f.argtypes = [i64, i32, i64, vp, vp, vp, i64, vp, sz, vp]
+            f.restype = i32
+        for f in (L.trbt_prepare_d, L.trbt_prepare_z):
+            f.argtypes = [i64, i32, vp, vp, vp, sz, vp]
             f.restype = i32
         L.trbt_strerror.argtypes = [i32]
         L.trbt_strerror.restype = C.c_char_p
@@ -110,6 +115,26 @@ def trans_ev_tridi_to_band_z(n, nbw, nev, hh_v, hh_tau, Z, ldz, work, work_bytes
     """Status-returning call of the C entry point (complex FP64)."""
     return lib().trans_ev_tridi_to_band_z(n, nbw, nev, _ptr(hh_v), _ptr(hh_tau), _ptr(Z), ldz,
                                           _ptr(work), work_bytes, _stream(stream))
+
+
+def trbt_prepare_d(n, nbw, hh_v, hh_tau, work, work_bytes, stream=None) -> int:
+    return lib().trbt_prepare_d(n, nbw, _ptr(hh_v), _ptr(hh_tau), _ptr(work), work_bytes,
+                                _stream(stream))
+
+
+def trbt_prepare_z(n, nbw, hh_v, hh_tau, work, work_bytes, stream=None) -> int:
+    return lib().trbt_prepare_z(n, nbw, _ptr(hh_v), _ptr(hh_tau), _ptr(work), work_bytes,
+                                _stream(stream))
+
+
+def trbt_apply_d(n, nbw, nev, hh_v, hh_tau, Z, ldz, work, work_bytes, stream=None) -> int:
+    return lib().trbt_apply_d(n, nbw, nev, _ptr(hh_v), _ptr(hh_tau), _ptr(Z), ldz, _ptr(work),
+                              work_bytes, _stream(stream))
+
+
+def trbt_apply_z(n, nbw, nev, hh_v, hh_tau, Z, ldz, work, work_bytes, stream=None) -> int:
+    return lib().trbt_apply_z(n, nbw, nev, _ptr(hh_v), _ptr(hh_tau), _ptr(Z), ldz, _ptr(work),
+                              work_bytes, _stream(stream))
 
 
 def alloc_workspace(n: int, nbw: int, nev: int, is_complex: bool, device="cuda"):

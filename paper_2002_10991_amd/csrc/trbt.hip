@@ -555,8 +555,43 @@ int validate(int64_t n, int nbw, int64_t nev, const void* hv, const void* ht, co
 }
 
 template <bool CPLX>
-int run(int64_t n, int nbw, int64_t nev, const double* hv, const double* ht, double* Z,
-        int64_t ldz, void* work, size_t work_bytes, void* stream_v)
+int prepare(int64_t n, int nbw, const double* hv, const double* ht, void* work,
+            size_t work_bytes, void* stream_v)
+{
+    if (n < 0) return -1;
+    if (nbw < 1 || nbw > TRBT_NBW_MAX) return -2;
+    const int64_t K = num_reflectors(n, nbw);
+    if (K > 0 && !hv) return -3;
+    if (K > 0 && !ht) return -4;
+    if (work && ((uintptr_t)work % TRBT_WORK_ALIGN)) return -5;
+    if (work_bytes && !work) return -5;
+    if (K == 0 || !blocked_eligible(nbw)) return TRBT_SUCCESS;
+    if (!work || work_bytes < blocked_bytes(n, nbw, CPLX)) return TRBT_ERR_WORKSPACE;
+    int rc = check_device();
+    if (rc) return rc;
+    hipStream_t st = (hipStream_t)stream_v;
+    double* ws = (double*)work;
+    const int64_t nblocks = blocked_num_blocks(n, nbw);
+    hipLaunchKernelGGL(k_zero_words, dim3(1), dim3(64), 0, st, (unsigned*)work, 64);
+#define TRBT_PACK(NBV)                                                                         \
+    case NBV:                                                                                  \
+        hipLaunchKernelGGL((k_pack<NBV, CPLX>), dim3((unsigned)nblocks), dim3(256), 0, st, n, \
+                           hv, ht, ws + HDR_BYTES / sizeof(double));                           \
+        break;
+    switch (nbw) {
+        TRBT_PACK(16)
+        TRBT_PACK(32)
+        TRBT_PACK(48)
+        TRBT_PACK(64)
+        default: return TRBT_ERR_INTERNAL;
+    }
+#undef TRBT_PACK
+    return hipGetLastError() == hipSuccess ? TRBT_SUCCESS : TRBT_ERR_HIP;
+}
+
+template <bool CPLX>
+int apply(int64_t n, int nbw, int64_t nev, const double* hv, const double* ht, double* Z,
+          int64_t ldz, void* work, size_t work_bytes, void* stream_v)
 {
     int rc = validate(n, nbw, nev, hv, ht, Z, ldz, work, work_bytes);
     if (rc) return rc;
@@ -567,27 +602,22 @@ int run(int64_t n, int nbw, int64_t nev, const double* hv, const double* ht, dou
 
     if (blocked_eligible(nbw)) {
         if (work_bytes < blocked_bytes(n, nbw, CPLX) || !work) return TRBT_ERR_WORKSPACE;
-        double* ws = (double*)work;
-        const int64_t nblocks = blocked_num_blocks(n, nbw);
-        const int64_t nevp = nev;
+        const double* ws = (const double*)work;
         const int CT = 1;
-        const int64_t strips = (nevp + 16 * CT - 1) / (16 * CT);
-        hipLaunchKernelGGL(k_zero_words, dim3(1), dim3(64), 0, st, (unsigned*)work, 64);
-#define TRBT_LAUNCH(NBV)                                                                       \
+        const int64_t strips = (nev + 16 * CT - 1) / (16 * CT);
+#define TRBT_MAIN(NBV)                                                                         \
     case NBV:                                                                                  \
-        hipLaunchKernelGGL((k_pack<NBV, CPLX>), dim3((unsigned)nblocks), dim3(256), 0, st, n, \
-                           hv, ht, ws + HDR_BYTES / sizeof(double));                           \
         hipLaunchKernelGGL((k_blocked<NBV, 1, CPLX>), dim3((unsigned)strips), dim3(64 * WAVES), \
-                           0, st, n, nev, (const double*)ws, Z, ldz, (unsigned*)work);         \
+                           0, st, n, nev, ws, Z, ldz, (unsigned*)work);                        \
         break;
         switch (nbw) {
-            TRBT_LAUNCH(16)
-            TRBT_LAUNCH(32)
-            TRBT_LAUNCH(48)
-            TRBT_LAUNCH(64)
+            TRBT_MAIN(16)
+            TRBT_MAIN(32)
+            TRBT_MAIN(48)
+            TRBT_MAIN(64)
             default: return TRBT_ERR_INTERNAL;
         }
-#undef TRBT_LAUNCH
+#undef TRBT_MAIN
     } else {
         const unsigned grid = (unsigned)((nev + 63) / 64);
         if (CPLX)
@@ -598,6 +628,19 @@ int run(int64_t n, int nbw, int64_t nev, const double* hv, const double* ht, dou
                                hv, ht, Z, ldz);
     }
     return hipGetLastError() == hipSuccess ? TRBT_SUCCESS : TRBT_ERR_HIP;
+}
+
+template <bool CPLX>
+int run(int64_t n, int nbw, int64_t nev, const double* hv, const double* ht, double* Z,
+        int64_t ldz, void* work, size_t work_bytes, void* stream_v)
+{
+    int rc = validate(n, nbw, nev, hv, ht, Z, ldz, work, work_bytes);
+    if (rc) return rc;
+    if (num_reflectors(n, nbw) == 0 || nev == 0) return TRBT_SUCCESS;
+    rc = prepare<CPLX>(n, nbw, hv, ht, work, work_bytes, stream_v);
+    if (rc == -5) return -8;           // work argument position differs
+    if (rc) return rc;
+    return apply<CPLX>(n, nbw, nev, hv, ht, Z, ldz, work, work_bytes, stream_v);
 }
 
 }  // namespace
@@ -647,6 +690,32 @@ int trans_ev_tridi_to_band_z(int64_t n, int nbw, int64_t nev, const trbt_z* hh_v
 {
     return run<true>(n, nbw, nev, (const double*)hh_v, (const double*)hh_tau, (double*)Z, ldz,
                      work, work_bytes, stream);
+}
+
+int trbt_prepare_d(int64_t n, int nbw, const double* hh_v, const double* hh_tau, void* work,
+                   size_t work_bytes, void* stream)
+{
+    return prepare<false>(n, nbw, hh_v, hh_tau, work, work_bytes, stream);
+}
+
+int trbt_prepare_z(int64_t n, int nbw, const trbt_z* hh_v, const trbt_z* hh_tau, void* work,
+                   size_t work_bytes, void* stream)
+{
+    return prepare<true>(n, nbw, (const double*)hh_v, (const double*)hh_tau, work, work_bytes,
+                         stream);
+}
+
+int trbt_apply_d(int64_t n, int nbw, int64_t nev, const double* hh_v, const double* hh_tau,
+                 double* Z, int64_t ldz, void* work, size_t work_bytes, void* stream)
+{
+    return apply<false>(n, nbw, nev, hh_v, hh_tau, Z, ldz, work, work_bytes, stream);
+}
+
+int trbt_apply_z(int64_t n, int nbw, int64_t nev, const trbt_z* hh_v, const trbt_z* hh_tau,
+                 trbt_z* Z, int64_t ldz, void* work, size_t work_bytes, void* stream)
+{
+    return apply<true>(n, nbw, nev, (const double*)hh_v, (const double*)hh_tau, (double*)Z, ldz,
+                       work, work_bytes, stream);
 }
 
 const char* trbt_strerror(int status)

@@ -2,8 +2,10 @@
 
 This module only draws random numbers in fixed, documented orders; it holds
 none of the method's arithmetic.  Both the GPU tests/benchmark and the CPU
-oracle take their inputs from here.  Where a generator needs reflector
-lengths, the caller passes them in.
+oracle take their inputs from here.  The reflector generator needs the
+number of valid entries of every stored reflector; ``reflector_lengths``
+states that input format (tests check it against the oracle and the
+library).
 
 Workloads (the paper's inputs are dense random Hermitian matrices and
 materials Hamiltonians whose back-transformation sees only (v, tau, X); these
@@ -18,6 +20,9 @@ shapes stand in for them):
   FD  real, n=64, nbw=8, nev=16                                   seed 3005
 """
 from __future__ import annotations
+
+import os
+from concurrent.futures import ThreadPoolExecutor
 
 import numpy as np
 
@@ -39,6 +44,38 @@ REFL_PER_CHUNK = 4096
 
 def _np_dtype(dtype: str):
     return np.complex128 if dtype == "z" else np.float64
+
+
+def _workers() -> int:
+    return max(1, min(16, len(os.sched_getaffinity(0))))
+
+
+def _parallel(fn, items):
+    """Run fn over independent chunks (each has its own seed, so the result
+    does not depend on the number of threads)."""
+    items = list(items)
+    if len(items) <= 1:
+        for it in items:
+            fn(it)
+        return
+    with ThreadPoolExecutor(_workers()) as ex:
+        list(ex.map(fn, items))
+
+
+def reflector_lengths(n: int, nbw: int) -> np.ndarray:
+    """Input-format bookkeeping: the number of valid entries of each stored
+    reflector, in storage order.  Stage s = 0..n-3 owns rows s+1..n-1, cut
+    into consecutive pieces of nbw rows; a trailing piece of a single row
+    carries no reflector (and nbw = 1 gives none at all)."""
+    if n < 3 or nbw < 2:
+        return np.zeros(0, np.int64)
+    out = []
+    for s in range(n - 2):
+        rows = n - s - 1
+        full, rest = divmod(rows, nbw)
+        piece = [nbw] * full + ([rest] if rest >= 2 else [])
+        out.append(np.array(piece, np.int64))
+    return np.concatenate(out)
 
 
 def band_matrix(n: int, nbw: int, seed: int, dtype: str = "d", diag_shift: bool = False):
@@ -91,15 +128,20 @@ def gaussian(n: int, ncols: int, seed: int, dtype: str = "d", cols=None) -> np.n
     need = {}
     for i, c in enumerate(cols):
         need.setdefault(int(c) // GAUSS_COLS_PER_CHUNK, []).append((i, int(c)))
-    for ch, items in need.items():
+
+    def fill(item):
+        ch, items = item
         rng = np.random.default_rng(seqs[ch])
         w = min(GAUSS_COLS_PER_CHUNK, ncols - ch * GAUSS_COLS_PER_CHUNK)
         if dtype == "z":
-            blk = np.sqrt(0.5) * (rng.standard_normal((w, n)) + 1j * rng.standard_normal((w, n)))
+            blk = rng.standard_normal((w, n)) + 1j * rng.standard_normal((w, n))
+            blk *= np.sqrt(0.5)
         else:
             blk = rng.standard_normal((w, n))
         for i, c in items:
             out[:, i] = blk[c - ch * GAUSS_COLS_PER_CHUNK]
+
+    _parallel(fill, need.items())
     return out
 
 
@@ -123,25 +165,28 @@ def unitary_reflectors(lengths: np.ndarray, nbw: int, seed: int, dtype: str = "d
     nchunk = (K + REFL_PER_CHUNK - 1) // REFL_PER_CHUNK
     seqs = np.random.SeedSequence(seed).spawn(max(nchunk, 1))
     col = np.arange(nbw)
-    for ch in range(nchunk):
+
+    def fill(ch):
         a, b = ch * REFL_PER_CHUNK, min(K, (ch + 1) * REFL_PER_CHUNK)
         rng = np.random.default_rng(seqs[ch])
         L = lengths[a:b]
         scale = 1.0 / np.sqrt(L.astype(np.float64))[:, None]
         if dtype == "z":
-            w = (rng.standard_normal((b - a, nbw)) + 1j * rng.standard_normal((b - a, nbw)))
+            w = rng.standard_normal((b - a, nbw)) + 1j * rng.standard_normal((b - a, nbw))
             w *= np.sqrt(0.5) * scale
             theta = rng.uniform(0.5 * np.pi, 1.5 * np.pi, b - a)
         else:
             w = rng.standard_normal((b - a, nbw)) * scale
         w[col[None, :] >= L[:, None]] = 0
         w[:, 0] = 1.0
-        nrm2 = np.sum(np.abs(w) ** 2, axis=1)
+        nrm2 = np.sum(w.real ** 2 + w.imag ** 2, axis=1) if dtype == "z" else np.sum(w * w, axis=1)
         V[a:b] = w
         if dtype == "z":
             tau[a:b] = (1.0 - np.exp(1j * theta)) / nrm2
         else:
             tau[a:b] = 2.0 / nrm2
+
+    _parallel(fill, range(nchunk))
     return V, tau
 
 
