@@ -337,19 +337,29 @@ __device__ inline d4 mfma(double a, double b, d4 c)
     return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
 }
 
+typedef double d2 __attribute__((ext_vector_type(2)));
+
+// Branch-free tile load: every lane reads a clamped, valid address and zeroes
+// what lies outside the matrix, so the 4 (8) loads issue back to back.
 template <bool CPLX>
 __device__ inline void load_tile(Tile<CPLX>& t, const double* __restrict__ Z, int64_t ldz,
                                  int64_t n, int64_t nev, int64_t row0, int64_t col)
 {
-    constexpr int NC = CPLX ? 2 : 1;
     const bool colok = col < nev;
+    const int64_t cc = colok ? col : nev - 1;
 #pragma unroll
     for (int e = 0; e < 4; ++e) {
         const int64_t r = row0 + 4 * e;
         const bool ok = colok && r >= 0 && r < n;
-        const double* p = Z + (col * ldz + r) * NC;
-        t.re[e] = ok ? p[0] : 0.0;
-        if constexpr (CPLX) t.im[e] = ok ? p[1] : 0.0;
+        const int64_t rr = r < 0 ? 0 : (r >= n ? n - 1 : r);
+        if constexpr (CPLX) {
+            const d2 x = *(const d2*)(Z + 2 * (cc * ldz + rr));
+            t.re[e] = ok ? x[0] : 0.0;
+            t.im[e] = ok ? x[1] : 0.0;
+        } else {
+            const double x = Z[cc * ldz + rr];
+            t.re[e] = ok ? x : 0.0;
+        }
     }
 }
 
@@ -357,20 +367,67 @@ template <bool CPLX>
 __device__ inline void store_tile(const Tile<CPLX>& t, double* __restrict__ Z, int64_t ldz,
                                   int64_t n, int64_t nev, int64_t row0, int64_t col)
 {
-    constexpr int NC = CPLX ? 2 : 1;
     if (col >= nev) return;
 #pragma unroll
     for (int e = 0; e < 4; ++e) {
         const int64_t r = row0 + 4 * e;
         if (r >= 0 && r < n) {
-            double* p = Z + (col * ldz + r) * NC;
-            p[0] = t.re[e];
-            if constexpr (CPLX) p[1] = t.im[e];
+            if constexpr (CPLX) {
+                *(d2*)(Z + 2 * (col * ldz + r)) = d2{t.re[e], t.im[e]};
+            } else {
+                Z[col * ldz + r] = t.re[e];
+            }
         }
     }
 }
 
-template <int NB, int CT, bool CPLX>
+// Spin (with s_sleep) until prog[idx] >= need.  A bounded wait: on the
+// never-expected timeout the wave flags the error word and gives up.
+__device__ inline bool wait_progress(int* prog, int idx, int need, unsigned* err, int lane)
+{
+    unsigned spins = 0;
+    while (__hip_atomic_load(&prog[idx], __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_WORKGROUP) < need) {
+        __builtin_amdgcn_s_sleep(2);
+        if (++spins > (1u << 26)) {
+            if (lane == 0) atomicOr(err, 1u);
+            return false;
+        }
+    }
+    return true;
+}
+
+// Offset (in doubles, from the block's packed data) of the c-th operand chunk
+// in the order the main kernel consumes them: first the 4*NT chunks of A1
+// (tile-major, (q,u) = (c/4, c%4)), then the 4*NT chunks of -V in u-major
+// order ((u,q) = (c2/NT, c2%NT)).
+template <int NB, bool CPLX>
+__host__ __device__ constexpr int chunk_offset(int c)
+{
+    using G = Geo<NB, CPLX>;
+    if (c < 4 * G::NT) return c * G::CHUNK;
+    const int c2 = c - 4 * G::NT, u = c2 / G::NT, q = c2 % G::NT;
+    return G::A1_DBL + (q * 4 + u) * G::CHUNK;
+}
+
+template <int NB, bool CPLX, int D>
+__device__ inline void load_chunk(const double* __restrict__ blkp, int c, int lane, double (&re)[D],
+                                  double (&im)[D], int slot)
+{
+    const double* p = blkp + chunk_offset<NB, CPLX>(c);
+    re[slot] = p[lane];
+    if constexpr (CPLX) im[slot] = p[64 + lane];
+}
+
+// Operand ring depth (chunks loaded ahead of use).  The ring position of a
+// chunk is its index in the block's stream modulo D, and the ring runs on
+// into the next block, so D must divide the chunk count per block.
+template <int NB, bool CPLX>
+__host__ __device__ constexpr int ring_depth()
+{
+    return CPLX ? 8 : 4 * Geo<NB, CPLX>::NT;
+}
+
+template <int NB, int CT, bool CPLX, int D>
 __global__ __launch_bounds__(64 * WAVES) void k_blocked(int64_t n, int64_t nev,
                                                         const double* __restrict__ ws,
                                                         double* __restrict__ Z, int64_t ldz,
@@ -378,114 +435,113 @@ __global__ __launch_bounds__(64 * WAVES) void k_blocked(int64_t n, int64_t nev,
 {
     using G = Geo<NB, CPLX>;
     constexpr int NT = G::NT;
+    constexpr int NCH = 8 * NT;            // operand chunks per block
+    static_assert(NCH % D == 0, "ring depth must divide the chunks per block");
     constexpr int64_t nt1 = NB / 16;
     __shared__ int prog[WAVES];
 
-    const int w = threadIdx.x / 64, lane = threadIdx.x % 64;
+    const int lane = threadIdx.x & 63;
+    const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     if (threadIdx.x < WAVES) prog[threadIdx.x] = 0;
     __syncthreads();
 
     const int64_t nblk = (n - 2 + KB - 1) / KB;
     const int64_t J = sweeps_in_stage(n, NB, 0);
-    const int64_t col_base = (int64_t)blockIdx.x * 16 * CT + lane % 16;
-    const int64_t rsub = lane / 16;
+    const int64_t col_base = (int64_t)blockIdx.x * 16 * CT + (lane & 15);
+    const int rsub = lane >> 4;
     const int wprev = (w + WAVES - 1) % WAVES;
     const double* __restrict__ wsb = ws + HDR_BYTES / sizeof(double);
 
     Tile<CPLX> zt[NT][CT];
+    double ring_re[D], ring_im[D];
 
     for (int64_t j = w; j < J; j += WAVES) {
         const int64_t t0 = j * nt1;
         const double* __restrict__ blkp = wsb + (size_t)slot_base(j, nblk, nt1) * G::PB;
-        for (int64_t t = t0; t < nblk; ++t, blkp += G::PB) {
-            if (j > 0) {
-                const int need = (int)((j - 1) * (nblk + 1) + t + 1);
-                unsigned spins = 0;
-                while (__hip_atomic_load(&prog[wprev], __ATOMIC_ACQUIRE,
-                                         __HIP_MEMORY_SCOPE_WORKGROUP) < need) {
-                    __builtin_amdgcn_s_sleep(2);
-                    if (++spins > (1u << 28)) {   // never expected: report and leave
-                        if (lane == 0) atomicOr(err, 1u);
-                        return;
-                    }
-                }
-            }
-            const int64_t p0 = n - 3 - KB * t - 15 + j * NB;
-            if (t == t0) {
+        const int need0 = (int)((j - 1) * (nblk + 1));   // + t + 1: slot j-1 done block t
+        if (j > 0 && !wait_progress(prog, wprev, need0 + (int)t0 + 1, err, lane)) return;
+        int64_t p0 = n - 3 - KB * t0 - 15 + j * NB;
 #pragma unroll
-                for (int q = 0; q < NT; ++q)
+        for (int q = 0; q < NT; ++q)
 #pragma unroll
-                    for (int c = 0; c < CT; ++c)
-                        load_tile<CPLX>(zt[q][c], Z, ldz, n, nev, p0 + 16 * q + rsub,
-                                        col_base + 16 * c);
-            } else {
+            for (int c = 0; c < CT; ++c)
+                load_tile<CPLX>(zt[q][c], Z, ldz, n, nev, p0 + 16 * q + rsub, col_base + 16 * c);
 #pragma unroll
-                for (int q = NT - 1; q > 0; --q)
-#pragma unroll
-                    for (int c = 0; c < CT; ++c) zt[q][c] = zt[q - 1][c];
+        for (int c = 0; c < D; ++c) load_chunk<NB, CPLX, D>(blkp, c, lane, ring_re, ring_im, c);
+
+        for (int64_t t = t0; t < nblk; ++t, blkp += G::PB, p0 -= KB) {
+            const bool has_next = t + 1 < nblk;
+            // the top tile of the next block: slot j-1 must have retired it
+            Tile<CPLX> znext[CT];
+            if (has_next) {
+                if (j > 0 && !wait_progress(prog, wprev, need0 + (int)t + 2, err, lane)) return;
 #pragma unroll
                 for (int c = 0; c < CT; ++c)
-                    load_tile<CPLX>(zt[0][c], Z, ldz, n, nev, p0 + rsub, col_base + 16 * c);
+                    load_tile<CPLX>(znext[c], Z, ldz, n, nev, p0 - 16 + rsub, col_base + 16 * c);
             }
 
-            // Y = A1 * Zwin
-            Tile<CPLX> y[CT];
+            Tile<CPLX> y[2][CT];   // two partial sums: more independent MFMA chains
 #pragma unroll
-            for (int c = 0; c < CT; ++c) {
-                y[c].re = d4{0.0, 0.0, 0.0, 0.0};
-                if constexpr (CPLX) y[c].im = d4{0.0, 0.0, 0.0, 0.0};
-            }
+            for (int h = 0; h < 2; ++h)
 #pragma unroll
-            for (int q = 0; q < NT; ++q) {
-#pragma unroll
-                for (int u = 0; u < 4; ++u) {
-                    const double* ap = blkp + (q * 4 + u) * G::CHUNK;
-                    const double ar = ap[lane];
-                    if constexpr (CPLX) {
-                        const double ai = ap[64 + lane];
-#pragma unroll
-                        for (int c = 0; c < CT; ++c) {
-                            y[c].re = mfma(ar, zt[q][c].re[u], y[c].re);
-                            y[c].im = mfma(ar, zt[q][c].im[u], y[c].im);
-                            y[c].re = mfma(-ai, zt[q][c].im[u], y[c].re);
-                            y[c].im = mfma(ai, zt[q][c].re[u], y[c].im);
-                        }
-                    } else {
-#pragma unroll
-                        for (int c = 0; c < CT; ++c) y[c].re = mfma(ar, zt[q][c].re[u], y[c].re);
-                    }
+                for (int c = 0; c < CT; ++c) {
+                    y[h][c].re = d4{0.0, 0.0, 0.0, 0.0};
+                    if constexpr (CPLX) y[h][c].im = d4{0.0, 0.0, 0.0, 0.0};
                 }
-            }
-            // Zwin += (-V) * Y
             Tile<CPLX> yn[CT];
-            if constexpr (CPLX) {
+
 #pragma unroll
-                for (int c = 0; c < CT; ++c) yn[c].re = -y[c].im;
-            }
+            for (int c = 0; c < NCH; ++c) {
+                const int slot = c % D;
+                const double ar = ring_re[slot];
+                const double ai = CPLX ? ring_im[slot] : 0.0;
+                if (c + D < NCH)
+                    load_chunk<NB, CPLX, D>(blkp, c + D, lane, ring_re, ring_im, slot);
+                else if (has_next)
+                    load_chunk<NB, CPLX, D>(blkp + G::PB, c + D - NCH, lane, ring_re, ring_im,
+                                            slot);
+                if (c < 4 * NT) {
+                    // Y += A1(:, chunk) * Zwin(chunk, :)
+                    const int q = c / 4, u = c % 4, h = q & 1;
 #pragma unroll
-            for (int u = 0; u < 4; ++u) {
-#pragma unroll
-                for (int q = 0; q < NT; ++q) {
-                    const double* vp = blkp + G::A1_DBL + (q * 4 + u) * G::CHUNK;
-                    const double vr = vp[lane];
-                    if constexpr (CPLX) {
-                        const double vi = vp[64 + lane];
-#pragma unroll
-                        for (int c = 0; c < CT; ++c) {
-                            zt[q][c].re = mfma(vr, y[c].re[u], zt[q][c].re);
-                            zt[q][c].im = mfma(vr, y[c].im[u], zt[q][c].im);
-                            zt[q][c].re = mfma(vi, yn[c].re[u], zt[q][c].re);
-                            zt[q][c].im = mfma(vi, y[c].re[u], zt[q][c].im);
+                    for (int cc = 0; cc < CT; ++cc) {
+                        if constexpr (CPLX) {
+                            y[h][cc].re = mfma(ar, zt[q][cc].re[u], y[h][cc].re);
+                            y[h][cc].im = mfma(ar, zt[q][cc].im[u], y[h][cc].im);
+                            y[h][cc].re = mfma(-ai, zt[q][cc].im[u], y[h][cc].re);
+                            y[h][cc].im = mfma(ai, zt[q][cc].re[u], y[h][cc].im);
+                        } else {
+                            y[h][cc].re = mfma(ar, zt[q][cc].re[u], y[h][cc].re);
                         }
-                    } else {
+                    }
+                } else {
+                    if (c == 4 * NT) {
 #pragma unroll
-                        for (int c = 0; c < CT; ++c)
-                            zt[q][c].re = mfma(vr, y[c].re[u], zt[q][c].re);
+                        for (int cc = 0; cc < CT; ++cc) {
+                            y[0][cc].re += y[1][cc].re;
+                            if constexpr (CPLX) {
+                                y[0][cc].im += y[1][cc].im;
+                                yn[cc].re = -y[0][cc].im;
+                            }
+                        }
+                    }
+                    // Zwin(tile q, :) += (-V)(tile q, chunk u) * Y(chunk u, :)
+                    const int c2 = c - 4 * NT, u = c2 / NT, q = c2 % NT;
+#pragma unroll
+                    for (int cc = 0; cc < CT; ++cc) {
+                        if constexpr (CPLX) {
+                            zt[q][cc].re = mfma(ar, y[0][cc].re[u], zt[q][cc].re);
+                            zt[q][cc].im = mfma(ar, y[0][cc].im[u], zt[q][cc].im);
+                            zt[q][cc].re = mfma(ai, yn[cc].re[u], zt[q][cc].re);
+                            zt[q][cc].im = mfma(ai, y[0][cc].re[u], zt[q][cc].im);
+                        } else {
+                            zt[q][cc].re = mfma(ar, y[0][cc].re[u], zt[q][cc].re);
+                        }
                     }
                 }
             }
 
-            if (t + 1 < nblk) {
+            if (has_next) {
 #pragma unroll
                 for (int c = 0; c < CT; ++c)
                     store_tile<CPLX>(zt[NT - 1][c], Z, ldz, n, nev, p0 + 16 * (NT - 1) + rsub,
@@ -500,6 +556,14 @@ __global__ __launch_bounds__(64 * WAVES) void k_blocked(int64_t n, int64_t nev,
             }
             __hip_atomic_store(&prog[w], (int)(j * (nblk + 1) + t + 1), __ATOMIC_RELEASE,
                                __HIP_MEMORY_SCOPE_WORKGROUP);
+            if (has_next) {
+#pragma unroll
+                for (int q = NT - 1; q > 0; --q)
+#pragma unroll
+                    for (int c = 0; c < CT; ++c) zt[q][c] = zt[q - 1][c];
+#pragma unroll
+                for (int c = 0; c < CT; ++c) zt[0][c] = znext[c];
+            }
         }
     }
 }
@@ -607,8 +671,9 @@ int apply(int64_t n, int nbw, int64_t nev, const double* hv, const double* ht, d
         const int64_t strips = (nev + 16 * CT - 1) / (16 * CT);
 #define TRBT_MAIN(NBV)                                                                         \
     case NBV:                                                                                  \
-        hipLaunchKernelGGL((k_blocked<NBV, 1, CPLX>), dim3((unsigned)strips), dim3(64 * WAVES), \
-                           0, st, n, nev, ws, Z, ldz, (unsigned*)work);                        \
+        hipLaunchKernelGGL((k_blocked<NBV, 1, CPLX, ring_depth<NBV, CPLX>()>),               \
+                           dim3((unsigned)strips),                                             \
+                           dim3(64 * WAVES), 0, st, n, nev, ws, Z, ldz, (unsigned*)work);      \
         break;
         switch (nbw) {
             TRBT_MAIN(16)
