@@ -187,8 +187,10 @@ struct Geo {
 // Packed for v_mfma_f64_16x16x4_f64 (A operand: lane i+16k holds A[i][k];
 // B operand: lane j+16k holds B[k][j]; accumulator: lane j+16g holds rows
 // g, g+4, g+8, g+12 of column j), chunk (q, u):
-//   A1 chunk lane l: A1[l%16][16q + 4u + l/16]
-//   -V chunk lane l: -Vt[16q + l%16][4u + l/16]
+//   A1 chunk lane l: A1[l%16][16q + 4u + l/16]     stored at position 4q+u
+//   -V chunk lane l: -Vt[16q + l%16][4u + l/16]    stored at position
+//                                                  4NT + u*NT + (NT-1-q)
+// i.e. in exactly the order the main kernel consumes them.
 // --------------------------------------------------------------------------
 template <int NB, bool CPLX>
 __global__ __launch_bounds__(256) void k_pack(int64_t n, const double* __restrict__ hv,
@@ -304,10 +306,12 @@ __global__ __launch_bounds__(256) void k_pack(int64_t n, const double* __restric
             out[qu * G::CHUNK + lane] = ar;
             if (CPLX) out[qu * G::CHUNK + 64 + lane] = ai;
         }
-        {
+        {   // -V chunks in the order the main kernel reads them: u ascending,
+            // and within each u the tiles from the bottom of the window up
             const int r = 16 * q + lane % 16, p = 4 * u + lane / 16;
-            out[G::A1_DBL + qu * G::CHUNK + lane] = -Vt[r][p][0];
-            if (CPLX) out[G::A1_DBL + qu * G::CHUNK + 64 + lane] = -Vt[r][p][NC - 1];
+            const int pos = u * NT + (NT - 1 - q);
+            out[G::A1_DBL + pos * G::CHUNK + lane] = -Vt[r][p][0];
+            if (CPLX) out[G::A1_DBL + pos * G::CHUNK + 64 + lane] = -Vt[r][p][NC - 1];
         }
     }
 }
@@ -339,12 +343,35 @@ __device__ inline d4 mfma(double a, double b, d4 c)
 
 typedef double d2 __attribute__((ext_vector_type(2)));
 
-// Branch-free tile load: every lane reads a clamped, valid address and zeroes
-// what lies outside the matrix, so the 4 (8) loads issue back to back.
+// MFMA with the FP64 negate modifiers of gfx950 (bit 0 negates A, bit 1 B).
+template <int NEG>
+__device__ inline d4 mfma_n(double a, double b, d4 c)
+{
+    return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, NEG);
+}
+
+// Tile load.  Interior tiles (all rows inside the matrix, whole strip inside
+// nev: a wave-uniform test) load directly; edge tiles read a clamped, valid
+// address and zero what lies outside, so all loads issue back to back.
 template <bool CPLX>
 __device__ inline void load_tile(Tile<CPLX>& t, const double* __restrict__ Z, int64_t ldz,
-                                 int64_t n, int64_t nev, int64_t row0, int64_t col)
+                                 int64_t n, int64_t nev, int64_t row0, int64_t col,
+                                 bool interior)
 {
+    if (interior) {
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+            const int64_t r = row0 + 4 * e;
+            if constexpr (CPLX) {
+                const d2 x = *(const d2*)(Z + 2 * (col * ldz + r));
+                t.re[e] = x[0];
+                t.im[e] = x[1];
+            } else {
+                t.re[e] = Z[col * ldz + r];
+            }
+        }
+        return;
+    }
     const bool colok = col < nev;
     const int64_t cc = colok ? col : nev - 1;
 #pragma unroll
@@ -396,28 +423,6 @@ __device__ inline bool wait_progress(int* prog, int idx, int need, unsigned* err
     return true;
 }
 
-// Offset (in doubles, from the block's packed data) of the c-th operand chunk
-// in the order the main kernel consumes them: first the 4*NT chunks of A1
-// (tile-major, (q,u) = (c/4, c%4)), then the 4*NT chunks of -V in u-major
-// order ((u,q) = (c2/NT, c2%NT)).
-template <int NB, bool CPLX>
-__host__ __device__ constexpr int chunk_offset(int c)
-{
-    using G = Geo<NB, CPLX>;
-    if (c < 4 * G::NT) return c * G::CHUNK;
-    const int c2 = c - 4 * G::NT, u = c2 / G::NT, q = c2 % G::NT;
-    return G::A1_DBL + (q * 4 + u) * G::CHUNK;
-}
-
-template <int NB, bool CPLX, int D>
-__device__ inline void load_chunk(const double* __restrict__ blkp, int c, int lane, double (&re)[D],
-                                  double (&im)[D], int slot)
-{
-    const double* p = blkp + chunk_offset<NB, CPLX>(c);
-    re[slot] = p[lane];
-    if constexpr (CPLX) im[slot] = p[64 + lane];
-}
-
 // Operand ring depth (chunks loaded ahead of use).  The ring position of a
 // chunk is its index in the block's stream modulo D, and the ring runs on
 // into the next block, so D must divide the chunk count per block.
@@ -427,47 +432,68 @@ __host__ __device__ constexpr int ring_depth()
     return CPLX ? 8 : 4 * Geo<NB, CPLX>::NT;
 }
 
-template <int NB, int CT, bool CPLX, int D>
-__global__ __launch_bounds__(64 * WAVES) void k_blocked(int64_t n, int64_t nev,
-                                                        const double* __restrict__ ws,
-                                                        double* __restrict__ Z, int64_t ldz,
-                                                        unsigned* __restrict__ err)
+template <bool CPLX, int D>
+__device__ inline void load_chunk(const double* __restrict__ blkp, int c, int lane,
+                                  double (&re)[D], double (&im)[D], int slot)
+{
+    constexpr int CH = CPLX ? 128 : 64;
+    const double* p = blkp + c * CH;
+    re[slot] = p[lane];
+    if constexpr (CPLX) im[slot] = p[64 + lane];
+}
+
+// Main blocked kernel.  Per block the operand stream is consumed in order:
+//   chunks 0 .. 4NT-1       A1 chunk (q, u) = (c/4, c%4):   Y += A1 * Zwin
+//   chunks 4NT .. 8NT-1     -V chunk (u, q), u ascending, q descending:
+//                           Zwin += (-V) * Y
+// During the last u pass (u = 3) each tile's final MFMA writes its result
+// one tile lower in the register window, so the slide of the window by one
+// tile costs no data movement; the bottom tile leaves as `zret`.
+template <int NB, int CT, bool CPLX, int D, int NW>
+__global__ __launch_bounds__(64 * NW) void k_blocked(int64_t n, int64_t nev,
+                                                     const double* __restrict__ ws,
+                                                     double* __restrict__ Z, int64_t ldz,
+                                                     unsigned* __restrict__ err)
 {
     using G = Geo<NB, CPLX>;
     constexpr int NT = G::NT;
     constexpr int NCH = 8 * NT;            // operand chunks per block
     static_assert(NCH % D == 0, "ring depth must divide the chunks per block");
     constexpr int64_t nt1 = NB / 16;
-    __shared__ int prog[WAVES];
+    __shared__ int prog[NW];
 
     const int lane = threadIdx.x & 63;
     const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-    if (threadIdx.x < WAVES) prog[threadIdx.x] = 0;
+    if (threadIdx.x < NW) prog[threadIdx.x] = 0;
     __syncthreads();
 
     const int64_t nblk = (n - 2 + KB - 1) / KB;
     const int64_t J = sweeps_in_stage(n, NB, 0);
     const int64_t col_base = (int64_t)blockIdx.x * 16 * CT + (lane & 15);
+    const bool cols_inside = (int64_t)(blockIdx.x + 1) * 16 * CT <= nev;
     const int rsub = lane >> 4;
-    const int wprev = (w + WAVES - 1) % WAVES;
+    const int wprev = (w + NW - 1) % NW;
     const double* __restrict__ wsb = ws + HDR_BYTES / sizeof(double);
 
     Tile<CPLX> zt[NT][CT];
     double ring_re[D], ring_im[D];
 
-    for (int64_t j = w; j < J; j += WAVES) {
+    for (int64_t j = w; j < J; j += NW) {
         const int64_t t0 = j * nt1;
         const double* __restrict__ blkp = wsb + (size_t)slot_base(j, nblk, nt1) * G::PB;
         const int need0 = (int)((j - 1) * (nblk + 1));   // + t + 1: slot j-1 done block t
         if (j > 0 && !wait_progress(prog, wprev, need0 + (int)t0 + 1, err, lane)) return;
         int64_t p0 = n - 3 - KB * t0 - 15 + j * NB;
 #pragma unroll
-        for (int q = 0; q < NT; ++q)
+        for (int q = 0; q < NT; ++q) {
+            const bool inside = cols_inside && p0 + 16 * q >= 0 && p0 + 16 * q + 16 <= n;
 #pragma unroll
             for (int c = 0; c < CT; ++c)
-                load_tile<CPLX>(zt[q][c], Z, ldz, n, nev, p0 + 16 * q + rsub, col_base + 16 * c);
+                load_tile<CPLX>(zt[q][c], Z, ldz, n, nev, p0 + 16 * q + rsub,
+                                col_base + 16 * c, inside);
+        }
 #pragma unroll
-        for (int c = 0; c < D; ++c) load_chunk<NB, CPLX, D>(blkp, c, lane, ring_re, ring_im, c);
+        for (int c = 0; c < D; ++c) load_chunk<CPLX, D>(blkp, c, lane, ring_re, ring_im, c);
 
         for (int64_t t = t0; t < nblk; ++t, blkp += G::PB, p0 -= KB) {
             const bool has_next = t + 1 < nblk;
@@ -475,9 +501,11 @@ __global__ __launch_bounds__(64 * WAVES) void k_blocked(int64_t n, int64_t nev,
             Tile<CPLX> znext[CT];
             if (has_next) {
                 if (j > 0 && !wait_progress(prog, wprev, need0 + (int)t + 2, err, lane)) return;
+                const bool inside = cols_inside && p0 - 16 >= 0 && p0 <= n;
 #pragma unroll
                 for (int c = 0; c < CT; ++c)
-                    load_tile<CPLX>(znext[c], Z, ldz, n, nev, p0 - 16 + rsub, col_base + 16 * c);
+                    load_tile<CPLX>(znext[c], Z, ldz, n, nev, p0 - 16 + rsub, col_base + 16 * c,
+                                    inside);
             }
 
             Tile<CPLX> y[2][CT];   // two partial sums: more independent MFMA chains
@@ -488,7 +516,7 @@ __global__ __launch_bounds__(64 * WAVES) void k_blocked(int64_t n, int64_t nev,
                     y[h][c].re = d4{0.0, 0.0, 0.0, 0.0};
                     if constexpr (CPLX) y[h][c].im = d4{0.0, 0.0, 0.0, 0.0};
                 }
-            Tile<CPLX> yn[CT];
+            Tile<CPLX> zsh[NT + 1][CT];   // window after the slide; zsh[NT] retires
 
 #pragma unroll
             for (int c = 0; c < NCH; ++c) {
@@ -496,46 +524,44 @@ __global__ __launch_bounds__(64 * WAVES) void k_blocked(int64_t n, int64_t nev,
                 const double ar = ring_re[slot];
                 const double ai = CPLX ? ring_im[slot] : 0.0;
                 if (c + D < NCH)
-                    load_chunk<NB, CPLX, D>(blkp, c + D, lane, ring_re, ring_im, slot);
+                    load_chunk<CPLX, D>(blkp, c + D, lane, ring_re, ring_im, slot);
                 else if (has_next)
-                    load_chunk<NB, CPLX, D>(blkp + G::PB, c + D - NCH, lane, ring_re, ring_im,
-                                            slot);
+                    load_chunk<CPLX, D>(blkp + G::PB, c + D - NCH, lane, ring_re, ring_im, slot);
                 if (c < 4 * NT) {
                     // Y += A1(:, chunk) * Zwin(chunk, :)
                     const int q = c / 4, u = c % 4, h = q & 1;
 #pragma unroll
                     for (int cc = 0; cc < CT; ++cc) {
                         if constexpr (CPLX) {
-                            y[h][cc].re = mfma(ar, zt[q][cc].re[u], y[h][cc].re);
-                            y[h][cc].im = mfma(ar, zt[q][cc].im[u], y[h][cc].im);
-                            y[h][cc].re = mfma(-ai, zt[q][cc].im[u], y[h][cc].re);
-                            y[h][cc].im = mfma(ai, zt[q][cc].re[u], y[h][cc].im);
+                            y[h][cc].re = mfma_n<0>(ar, zt[q][cc].re[u], y[h][cc].re);
+                            y[h][cc].im = mfma_n<0>(ar, zt[q][cc].im[u], y[h][cc].im);
+                            y[h][cc].re = mfma_n<1>(ai, zt[q][cc].im[u], y[h][cc].re);
+                            y[h][cc].im = mfma_n<0>(ai, zt[q][cc].re[u], y[h][cc].im);
                         } else {
-                            y[h][cc].re = mfma(ar, zt[q][cc].re[u], y[h][cc].re);
+                            y[h][cc].re = mfma_n<0>(ar, zt[q][cc].re[u], y[h][cc].re);
                         }
                     }
-                } else {
-                    if (c == 4 * NT) {
+                    if (c == 4 * NT - 1) {
 #pragma unroll
                         for (int cc = 0; cc < CT; ++cc) {
                             y[0][cc].re += y[1][cc].re;
-                            if constexpr (CPLX) {
-                                y[0][cc].im += y[1][cc].im;
-                                yn[cc].re = -y[0][cc].im;
-                            }
+                            if constexpr (CPLX) y[0][cc].im += y[1][cc].im;
                         }
                     }
+                } else {
                     // Zwin(tile q, :) += (-V)(tile q, chunk u) * Y(chunk u, :)
-                    const int c2 = c - 4 * NT, u = c2 / NT, q = c2 % NT;
+                    const int c2 = c - 4 * NT, u = c2 / NT, q = NT - 1 - c2 % NT;
 #pragma unroll
                     for (int cc = 0; cc < CT; ++cc) {
+                        const Tile<CPLX>& src = zt[q][cc];
+                        Tile<CPLX>& dst = (u == 3) ? zsh[q + 1][cc] : zt[q][cc];
                         if constexpr (CPLX) {
-                            zt[q][cc].re = mfma(ar, y[0][cc].re[u], zt[q][cc].re);
-                            zt[q][cc].im = mfma(ar, y[0][cc].im[u], zt[q][cc].im);
-                            zt[q][cc].re = mfma(ai, yn[cc].re[u], zt[q][cc].re);
-                            zt[q][cc].im = mfma(ai, y[0][cc].re[u], zt[q][cc].im);
+                            const d4 re = mfma_n<0>(ar, y[0][cc].re[u], src.re);
+                            const d4 im = mfma_n<0>(ar, y[0][cc].im[u], src.im);
+                            dst.re = mfma_n<2>(ai, y[0][cc].im[u], re);
+                            dst.im = mfma_n<0>(ai, y[0][cc].re[u], im);
                         } else {
-                            zt[q][cc].re = mfma(ar, y[0][cc].re[u], zt[q][cc].re);
+                            dst.re = mfma_n<0>(ar, y[0][cc].re[u], src.re);
                         }
                     }
                 }
@@ -544,23 +570,23 @@ __global__ __launch_bounds__(64 * WAVES) void k_blocked(int64_t n, int64_t nev,
             if (has_next) {
 #pragma unroll
                 for (int c = 0; c < CT; ++c)
-                    store_tile<CPLX>(zt[NT - 1][c], Z, ldz, n, nev, p0 + 16 * (NT - 1) + rsub,
+                    store_tile<CPLX>(zsh[NT][c], Z, ldz, n, nev, p0 + 16 * (NT - 1) + rsub,
                                      col_base + 16 * c);
             } else {
 #pragma unroll
                 for (int q = 0; q < NT; ++q)
 #pragma unroll
                     for (int c = 0; c < CT; ++c)
-                        store_tile<CPLX>(zt[q][c], Z, ldz, n, nev, p0 + 16 * q + rsub,
+                        store_tile<CPLX>(zsh[q + 1][c], Z, ldz, n, nev, p0 + 16 * q + rsub,
                                          col_base + 16 * c);
             }
             __hip_atomic_store(&prog[w], (int)(j * (nblk + 1) + t + 1), __ATOMIC_RELEASE,
                                __HIP_MEMORY_SCOPE_WORKGROUP);
             if (has_next) {
 #pragma unroll
-                for (int q = NT - 1; q > 0; --q)
+                for (int q = 1; q < NT; ++q)
 #pragma unroll
-                    for (int c = 0; c < CT; ++c) zt[q][c] = zt[q - 1][c];
+                    for (int c = 0; c < CT; ++c) zt[q][c] = zsh[q][c];
 #pragma unroll
                 for (int c = 0; c < CT; ++c) zt[0][c] = znext[c];
             }
@@ -671,7 +697,7 @@ int apply(int64_t n, int nbw, int64_t nev, const double* hv, const double* ht, d
         const int64_t strips = (nev + 16 * CT - 1) / (16 * CT);
 #define TRBT_MAIN(NBV)                                                                         \
     case NBV:                                                                                  \
-        hipLaunchKernelGGL((k_blocked<NBV, 1, CPLX, ring_depth<NBV, CPLX>()>),               \
+        hipLaunchKernelGGL((k_blocked<NBV, 1, CPLX, ring_depth<NBV, CPLX>(), WAVES>),               \
                            dim3((unsigned)strips),                                             \
                            dim3(64 * WAVES), 0, st, n, nev, ws, Z, ldz, (unsigned*)work);      \
         break;
