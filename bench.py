@@ -80,6 +80,24 @@ def cpu_baseline(cfg, V, tau, Z, L_total, budget_s=20.0):
                       f"{dt:.1f} s wall; rate scales to all columns (columns are independent)"}
 
 
+def committed_traffic(workload: str):
+    """HBM bytes per launch of the apply kernel from the committed rocprofv3
+    counter summary, if it was taken on the current kernel source; else None."""
+    import hashlib
+    prof = os.path.join(ROOT, "profiles", f"k_blocked_{workload}.md")
+    src = os.path.join(ROOT, "paper_2002_10991_amd", "csrc", "trbt.hip")
+    if not os.path.exists(prof):
+        return None
+    text = open(prof).read()
+    sha = hashlib.sha256(open(src, "rb").read()).hexdigest()
+    if f"source_sha256: {sha}" not in text:
+        return None
+    for line in text.splitlines():
+        if line.startswith("traffic_bytes_per_launch:"):
+            return float(line.split(":", 1)[1])
+    return None
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -189,7 +207,8 @@ def main():
         },
         "roofline": {
             "bound": "mfma", "achieved": round(achieved, 4), "peak": PEAK_FP64_TFLOPS,
-            "unit": "TFLOP/s", "frac": round(achieved / PEAK_FP64_TFLOPS, 4), "traffic": None,
+            "unit": "TFLOP/s", "frac": round(achieved / PEAK_FP64_TFLOPS, 4),
+            "traffic": committed_traffic(args.workload),
             "kernel": "k_blocked (apply)",
         },
     }

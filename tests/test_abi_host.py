@@ -1,0 +1,115 @@
+"""Host-side checks of the C ABI (no GPU needed): the library loads and
+exports every function include/trbt.h declares, argument validation returns
+the documented codes before anything is launched, and the host helpers agree
+with the oracle's reflector geometry."""
+import os
+import re
+
+import numpy as np
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "trbt.h")
+
+
+@pytest.fixture(scope="module")
+def T():
+    import paper_2002_10991_amd as T
+    if not os.path.exists(T.LIB_PATH):
+        from paper_2002_10991_amd import build
+        build.build()
+    T.lib()
+    return T
+
+
+def _declared_functions():
+    src = open(HEADER).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    names = re.findall(r"^\s*(?:const\s+)?[A-Za-z_][\w\s\*]*?\b([a-z_][a-z0-9_]*)\s*\(", src, re.M)
+    return sorted(set(n for n in names if not n.startswith("defined")))
+
+
+def test_every_declared_symbol_is_exported(T):
+    names = _declared_functions()
+    assert {"trans_ev_tridi_to_band_d", "trans_ev_tridi_to_band_z", "trbt_prepare_d",
+            "trbt_apply_z", "trbt_workspace_bytes", "trbt_strerror"} <= set(names)
+    lib = T.lib()
+    for n in names:
+        assert hasattr(lib, n), n
+
+
+# one invalid argument per case; every earlier argument valid, so the call
+# returns from host validation before any HIP call
+FAKE = 4096   # never dereferenced: validation fails first
+
+
+@pytest.mark.parametrize("fn", ["trans_ev_tridi_to_band_d", "trans_ev_tridi_to_band_z",
+                                "trbt_apply_d", "trbt_apply_z"])
+def test_argument_validation_codes(T, fn):
+    f = getattr(T, fn)
+    ok = dict(n=100, nbw=32, nev=10, hh_v=FAKE, hh_tau=FAKE, Z=FAKE, ldz=100, work=None, work_bytes=0)
+
+    def call(**kw):
+        a = dict(ok, **kw)
+        return f(a["n"], a["nbw"], a["nev"], a["hh_v"], a["hh_tau"], a["Z"], a["ldz"],
+                 a["work"], a["work_bytes"], 0)
+
+    assert call(n=-1) == -1
+    assert call(nbw=0) == -2
+    assert call(nbw=257) == -2
+    assert call(nev=-1) == -3
+    assert call(nev=101) == -3
+    assert call(hh_v=None) == -4
+    assert call(hh_tau=None) == -5
+    assert call(Z=None) == -6
+    assert call(ldz=99) == -7
+    assert call(work=FAKE + 8) == -8          # misaligned
+    assert call(work=None, work_bytes=64) == -8
+    # quick returns touch nothing and need no device
+    assert call(nev=0, hh_v=None, hh_tau=None, Z=None) == 0
+    assert call(n=2, nev=2, ldz=2) == 0
+    assert call(nbw=1, hh_v=None, hh_tau=None) == 0
+
+
+@pytest.mark.parametrize("fn", ["trbt_prepare_d", "trbt_prepare_z"])
+def test_prepare_validation_codes(T, fn):
+    f = getattr(T, fn)
+    assert f(-1, 32, FAKE, FAKE, None, 0, 0) == -1
+    assert f(100, 0, FAKE, FAKE, None, 0, 0) == -2
+    assert f(100, 32, None, FAKE, None, 0, 0) == -3
+    assert f(100, 32, FAKE, None, None, 0, 0) == -4
+    assert f(100, 32, FAKE, FAKE, FAKE + 8, 64, 0) == -5
+    assert f(100, 32, FAKE, FAKE, None, 0, 0) == -101     # blocked shape needs workspace
+    assert f(100, 7, FAKE, FAKE, None, 0, 0) == 0         # unblocked shape: nothing to do
+    assert f(2, 32, None, None, None, 0, 0) == 0
+
+
+@pytest.mark.parametrize("n,nbw", [(17, 4), (300, 7), (1000, 64), (3, 2), (5, 1), (64, 8)])
+def test_geometry_helpers_match_oracle(T, oracle_mod, n, nbw):
+    K = T.trbt_num_reflectors(n, nbw)
+    assert K == oracle_mod.num_reflectors(n, nbw)
+    off = T.trbt_stage_offsets(n, nbw)
+    expect = np.zeros(n - 1, np.int64)
+    for s in range(n - 2):
+        expect[s + 1] = expect[s] + oracle_mod.sweeps_in_stage(n, nbw, s)
+    assert np.array_equal(off, expect)
+    assert off[-1] == K
+
+
+def test_workspace_query(T):
+    assert T.trbt_workspace_bytes(1000, 7, 100, False) == 0
+    assert T.trbt_workspace_bytes(1000, 64, 0, True) == 0
+    a = T.trbt_workspace_bytes(1000, 64, 100, False)
+    b = T.trbt_workspace_bytes(1000, 64, 100, True)
+    c = T.trbt_workspace_bytes(2000, 64, 100, True)
+    assert 0 < a < b < c
+    assert T.trbt_workspace_bytes(1000, 64, 5, True) == b     # independent of nev > 0
+    with pytest.raises(T.TrbtError):
+        T.trbt_workspace_bytes(10, 300, 1, False)
+
+
+def test_strerror(T):
+    assert T.trbt_strerror(0) == "success"
+    assert "gfx950" in T.trbt_strerror(-100)
+    assert "workspace" in T.trbt_strerror(-101)
+    assert "argument" in T.trbt_strerror(-3)

@@ -1,0 +1,93 @@
+"""GPU parity at the workload sizes, in the launch configuration the
+benchmark times (prepare + apply through the C ABI), on sampled columns the
+oracle computes one by one (columns are independent, Sec. 2.2.2).
+
+Full-size inputs are the seeded synthetic unitary reflectors (the CPU bulge
+chase at n = 8192 / 32768 takes minutes to hours); chase-produced reflectors
+are covered at n <= 2048 here and in test_gpu_parity.py."""
+import numpy as np
+import pytest
+
+from conftest import gpu_available
+
+pytestmark = [pytest.mark.gpu,
+              pytest.mark.skipif(not gpu_available(), reason="needs a GPU")]
+
+TOL = 1e-12
+
+
+def _run_prepare_apply(n, nbw, nev, V, tau, Z):
+    import torch
+
+    import paper_2002_10991_amd as T
+    cplx = np.iscomplexobj(Z)
+    dev = torch.device("cuda:0")
+    Vd = torch.from_numpy(V).to(dev)
+    td = torch.from_numpy(tau).to(dev)
+    Zbuf = torch.from_numpy(np.ascontiguousarray(Z.T)).to(dev)
+    work = T.alloc_workspace(n, nbw, nev, cplx, dev)
+    wb = 0 if work is None else work.numel()
+    prep = T.trbt_prepare_z if cplx else T.trbt_prepare_d
+    appl = T.trbt_apply_z if cplx else T.trbt_apply_d
+    print(f"[gpu] prepare+apply n={n} nbw={nbw} nev={nev} {'z' if cplx else 'd'}", flush=True)
+    assert prep(n, nbw, Vd, td, work, wb) == 0
+    assert appl(n, nbw, nev, Vd, td, Zbuf, n, work, wb) == 0
+    torch.cuda.synchronize()
+    if work is not None:
+        assert int(work[:4].view(torch.int32).cpu()[0]) == 0
+    return Zbuf
+
+
+def _sampled_check(oracle_mod, Zbuf, Z, V, tau, nbw, cols):
+    out = Zbuf[cols].cpu().numpy().T
+    ref = oracle_mod.back_transform(Z[:, cols], V, tau, nbw)
+    err = np.linalg.norm(out - ref) / np.linalg.norm(ref)
+    print(f"[gpu] sampled columns {list(cols)}: rel err {err:.2e}", flush=True)
+    assert err <= TOL
+    # the whole result stays an isometric image of the input
+    nz = float(np.linalg.norm(Z))
+    ny = float(np.linalg.norm(Zbuf.cpu().numpy()))
+    assert abs(ny - nz) <= 1e-12 * nz
+
+
+@pytest.mark.parametrize("cfg", ["C2", "C3"])
+def test_full_size_sampled_columns(oracle_mod, cfg):
+    import synth
+    c = dict(C2=dict(n=8192, nbw=64, nev=4096, dtype="d", seed=1002),
+             C3=dict(n=32768, nbw=64, nev=8192, dtype="z", seed=1003))[cfg]
+    n, nbw, nev, dt = c["n"], c["nbw"], c["nev"], c["dtype"]
+    lengths = synth.reflector_lengths(n, nbw)
+    V, tau = synth.unitary_reflectors(lengths, nbw, c["seed"], dt)
+    Z = synth.gaussian(n, nev, c["seed"] + 1, dt)
+    Zbuf = _run_prepare_apply(n, nbw, nev, V, tau, Z)
+    # first, last, strip and slot-group boundaries, and a few inside
+    cols = np.unique(np.array([0, 1, 15, 16, 17, nev // 2, nev - 17, nev - 1,
+                               *np.random.default_rng(7).integers(0, nev, 8)]))
+    _sampled_check(oracle_mod, Zbuf, Z, V, tau, nbw, cols)
+
+
+@pytest.mark.parametrize("dtype", ["d", "z"])
+def test_chase_reflectors_n2048_nbw64(oracle_mod, dtype):
+    import synth
+    n, nbw, nev = 2048, 64, 300
+    ab = synth.band_matrix(n, nbw, 4242, dtype, diag_shift=True)
+    r = oracle_mod.band_to_tridiagonal(ab, nbw)
+    Z = synth.gaussian(n, nev, 4243, dtype)
+    Zbuf = _run_prepare_apply(n, nbw, nev, r["hh_v"], r["hh_tau"], Z)
+    out = Zbuf.cpu().numpy().T
+    ref = oracle_mod.back_transform(Z, r["hh_v"], r["hh_tau"], nbw)
+    assert np.linalg.norm(out - ref) / np.linalg.norm(ref) <= TOL
+
+
+def test_max_nev_ragged_strips(oracle_mod):
+    """nev = n (the largest allowed) with n not a multiple of 16 and a last
+    strip of 5 columns."""
+    import synth
+    n, nbw = 1045, 32
+    lengths = synth.reflector_lengths(n, nbw)
+    V, tau = synth.unitary_reflectors(lengths, nbw, 99, "z")
+    Z = synth.gaussian(n, n, 100, "z")
+    Zbuf = _run_prepare_apply(n, nbw, n, V, tau, Z)
+    out = Zbuf.cpu().numpy().T
+    ref = oracle_mod.back_transform(Z, V, tau, nbw)
+    assert np.linalg.norm(out - ref) / np.linalg.norm(ref) <= TOL
