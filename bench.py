@@ -80,6 +80,84 @@ def cpu_baseline(cfg, V, tau, Z, L_total, budget_s=20.0):
                       f"{dt:.1f} s wall; rate scales to all columns (columns are independent)"}
 
 
+def c4_inputs():
+    """The batched workload: 64 real problems, n_p = 512*U{1..8} (seed 1004),
+    nbw = 32, nev = n_p/2, per-problem seeds from SeedSequence(1004)."""
+    import synth
+    sizes, seeds = synth.batched_sizes(), synth.batched_seeds()
+    out = []
+    for n, sd in zip(sizes, seeds):
+        n = int(n)
+        lengths = synth.reflector_lengths(n, 32)
+        V, tau = synth.unitary_reflectors(lengths, 32, sd, "d")
+        Z = synth.gaussian(n, n // 2, sd + 1, "d")
+        out.append((n, 32, n // 2, int(lengths.sum()), V, tau, Z))
+    return out
+
+
+def batched_leg(steps: int, warmup: int):
+    """Batched plan (one persistent graph-captured launch, autotuned) against
+    64 looped single-problem calls on one stream, same inputs, same stream."""
+    import torch
+    import paper_2002_10991_amd as T
+    dev = torch.device("cuda:0")
+    t = time.perf_counter()
+    probs = c4_inputs()
+    log(f"C4 inputs ready in {time.perf_counter() - t:.1f}s")
+    flops = sum(4 * nev * L for n, nbw, nev, L, V, tau, Z in probs)
+    tensors = []
+    for n, nbw, nev, L, V, tau, Z in probs:
+        tensors.append((torch.from_numpy(np.ascontiguousarray(Z.T)).to(dev),
+                        torch.from_numpy(V).to(dev), torch.from_numpy(tau).to(dev), nbw))
+    stream = torch.cuda.current_stream()
+    wmax = max(T.trbt_workspace_bytes(n, nbw, nev, False) for n, nbw, nev, *_ in probs)
+    work = torch.empty(wmax + T.TRBT_WORK_ALIGN, dtype=torch.uint8, device=dev)
+    work = work[(-work.data_ptr()) % T.TRBT_WORK_ALIGN:][:wmax]
+
+    def looped():
+        for Zb, Vd, td, nbw in tensors:
+            n, nev = Zb.shape[1], Zb.shape[0]
+            rc = T.trans_ev_tridi_to_band_d(n, nbw, nev, Vd, td, Zb, n, work, wmax, stream)
+            if rc:
+                raise T.TrbtError(rc, "trans_ev_tridi_to_band_d")
+
+    t = time.perf_counter()
+    plan = T.BatchedPlan([(Zb.T, Vd, td, nbw) for Zb, Vd, td, nbw in tensors], None, stream)
+    create_s = time.perf_counter() - t
+    cfg, tuned_ms = plan.config
+    log(f"C4 plan created in {create_s:.2f}s, tuned config {cfg} ({tuned_ms:.3f} ms)")
+
+    def timed(fn):
+        for _ in range(warmup):
+            fn()
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        for _ in range(steps):
+            fn()
+        e1.record(stream)
+        torch.cuda.synchronize()
+        return e0.elapsed_time(e1) / steps
+
+    loop_ms = timed(looped)
+    log(f"C4 looped: {loop_ms:.3f} ms per batch")
+    batch_ms = timed(plan.run)
+    log(f"C4 batched: {batch_ms:.3f} ms per batch")
+    if plan.fault():
+        raise RuntimeError("batched plan: device wait-timeout flag set")
+    plan.close()
+    return {
+        "workload": "C4: 64 real problems, n_p = 512*U{1..8} (seed 1004), nbw=32, nev=n_p/2",
+        "flops_per_batch": flops,
+        "batched_ms": round(batch_ms, 4), "looped_ms": round(loop_ms, 4),
+        "batched_tflops": round(flops / batch_ms / 1e9, 4),
+        "looped_tflops": round(flops / loop_ms / 1e9, 4),
+        "speedup": round(loop_ms / batch_ms, 3),
+        "tuned_config": {"strip_cols": cfg[0], "waves": cfg[1], "block_stages": cfg[2]},
+        "plan_create_s": round(create_s, 3),
+    }
+
+
 def committed_traffic(workload: str):
     """HBM bytes per launch of the apply kernel from the committed rocprofv3
     counter summary, if it was taken on the current kernel source; else None."""
@@ -105,6 +183,10 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", default="C3", choices=sorted(WORKLOADS))
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-batched", action="store_true",
+                    help="skip the batched-vs-looped comparison on the 64-problem workload")
+    ap.add_argument("--batched-only", action="store_true",
+                    help="run only the batched-vs-looped comparison and print its JSON")
     ap.add_argument("--copy-kernel", type=int, default=0, metavar="BYTES",
                     help="only run one plain device-to-device copy of BYTES bytes (used to "
                          "calibrate the FETCH_SIZE / WRITE_SIZE counters) and exit")
@@ -126,6 +208,10 @@ def main():
 
     import torch
     import paper_2002_10991_amd as T
+
+    if args.batched_only:
+        print(json.dumps({"batched_vs_loop": batched_leg(args.steps, args.warmup)}), flush=True)
+        return
 
     cfg = WORKLOADS[args.workload]
     n, nbw, nev, dt = cfg["n"], cfg["nbw"], cfg["nev"], cfg["dtype"]
@@ -212,6 +298,8 @@ def main():
             "kernel": "k_blocked (apply)",
         },
     }
+    if not args.no_batched:
+        out["batched_vs_loop"] = batched_leg(args.steps, args.warmup)
     if not args.no_cpu_baseline:
         log("timing the CPU oracle on a column sample")
         out["cpu_baseline"] = cpu_baseline(cfg, V, tau, Z, L_total)

@@ -124,6 +124,82 @@ int trbt_apply_d(int64_t n, int nbw, int64_t nev, const double *hh_v, const doub
 int trbt_apply_z(int64_t n, int nbw, int64_t nev, const trbt_z *hh_v, const trbt_z *hh_tau,
                  trbt_z *Z, int64_t ldz, void *work, size_t work_bytes, void *stream);
 
+/* ------------------------------------------------------------------------
+ * Batched back-transformation: many independent real problems of uneven
+ * size (k-points, spin channels), each exactly the operation above, run
+ * through one persistent launch per band width, captured once in a HIP graph.
+ * ------------------------------------------------------------------------ */
+
+/* One problem: the arguments of trans_ev_tridi_to_band_d.  All pointers are
+ * device pointers owned by the caller.  Distinct problems must not share
+ * Z storage. */
+typedef struct {
+    int64_t n;
+    int nbw;
+    int64_t nev;
+    const double *hh_v;
+    const double *hh_tau;
+    double *Z;
+    int64_t ldz;
+} trbt_problem_d;
+
+/* Launch configuration of a plan.
+ *   strip_cols    columns of Z per workgroup task: 16 or 32;
+ *   waves         wavefronts per workgroup (slots in flight): 4 or 8;
+ *   block_stages  16: compact-WY blocks of 16 consecutive stages on FP64
+ *                 MFMA (problems with nbw in {16, 32, 48, 64}; other nbw
+ *                 fall back to the streaming form); 1: every problem with
+ *                 the streaming form, one reflector at a time, one lane per
+ *                 column (strip_cols and waves then do not matter). */
+typedef struct {
+    int strip_cols;
+    int waves;
+    int block_stages;
+} trbt_plan_config;
+
+typedef struct trbt_plan trbt_plan;   /* opaque */
+
+/* Status of a problem descriptor that fails the single-call checks. */
+#define TRBT_ERR_PROBLEM(i) (-1000 - (i))
+
+/* Create a plan for `count` problems on the current device.
+ * Arguments: 1 probs (host array, copied; non-NULL unless count == 0),
+ * 2 count >= 0, 3 cfg (host; NULL = autotune, see below; otherwise checked
+ * against the values listed above), 4 plan (out, set to NULL on failure),
+ * 5 stream.  Descriptor i failing the checks of trans_ev_tridi_to_band_d
+ * returns TRBT_ERR_PROBLEM(i).
+ * Blocking call: it synchronizes `stream` (which may still be producing the
+ * inputs), allocates the plan's device memory (header, packed compact-WY
+ * blocks of every problem, task tables; the only allocation of the plan's
+ * life) and captures the launch sequence into a graph.  With cfg == NULL it
+ * first times every candidate configuration on device scratch copies of the
+ * problems' Z (freed before returning) and keeps the fastest; the caller's
+ * Z is not modified. */
+int trbt_plan_create_batched_d(const trbt_problem_d *probs, int count,
+                               const trbt_plan_config *cfg, trbt_plan **plan,
+                               void *stream);
+
+/* Run the plan on `stream`: every problem's Z <- Q_i^* Z, in place.
+ * The plan keeps the descriptors and pointers given at creation: buffer
+ * contents (Z, hh_v, hh_tau) may change between executions, addresses may
+ * not.  Executions of one plan must not overlap in time (they share the
+ * plan's device state); ordering them on one stream is enough.
+ * Errors: -1 null plan, TRBT_ERR_DEVICE (another device is current),
+ * TRBT_ERR_HIP. */
+int trbt_plan_exec(trbt_plan *plan, void *stream);
+
+/* The configuration in use and, if tuned, the best measured time of one
+ * execution in milliseconds (0 when the configuration was given). */
+int trbt_plan_get_config(const trbt_plan *plan, trbt_plan_config *cfg, double *tuned_ms);
+
+/* Synchronize the device and report the plan's fault word: 0 when every
+ * bounded inter-wave wait of the last execution completed (nonzero never
+ * expected; the results are then invalid). */
+int trbt_plan_check(trbt_plan *plan, int *fault);
+
+/* Free the plan (synchronizes the device first).  NULL is accepted. */
+int trbt_plan_destroy(trbt_plan *plan);
+
 /* Static description of a status code (never NULL). */
 const char *trbt_strerror(int status);
 

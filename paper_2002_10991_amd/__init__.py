@@ -20,7 +20,9 @@ __all__ = [
     "TrbtError", "lib", "trbt_num_reflectors", "trbt_stage_offsets", "trbt_workspace_bytes",
     "trans_ev_tridi_to_band_d", "trans_ev_tridi_to_band_z", "trbt_prepare_d", "trbt_prepare_z",
     "trbt_apply_d", "trbt_apply_z", "trbt_strerror", "back_transform", "alloc_workspace",
-    "TRBT_WORK_ALIGN", "TRBT_NBW_MAX",
+    "TRBT_WORK_ALIGN", "TRBT_NBW_MAX", "trbt_problem_d", "trbt_plan_config",
+    "trbt_plan_create_batched_d", "trbt_plan_exec", "trbt_plan_get_config", "trbt_plan_check",
+    "trbt_plan_destroy", "BatchedPlan",
 ]
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
@@ -28,6 +30,17 @@ LIB_PATH = os.path.join(_HERE, "libtrbt.so")
 TRBT_WORK_ALIGN = 256
 TRBT_NBW_MAX = 256
 _lib = None
+
+
+class trbt_problem_d(C.Structure):
+    """One problem of a batched plan (device pointers as integers)."""
+    _fields_ = [("n", C.c_int64), ("nbw", C.c_int), ("nev", C.c_int64),
+                ("hh_v", C.c_void_p), ("hh_tau", C.c_void_p), ("Z", C.c_void_p),
+                ("ldz", C.c_int64)]
+
+
+class trbt_plan_config(C.Structure):
+    _fields_ = [("strip_cols", C.c_int), ("waves", C.c_int), ("block_stages", C.c_int)]
 
 
 class TrbtError(RuntimeError):
@@ -54,6 +67,19 @@ def lib():
         for f in (L.trbt_prepare_d, L.trbt_prepare_z):
             f.argtypes = [i64, i32, vp, vp, vp, sz, vp]
             f.restype = i32
+        L.trbt_plan_create_batched_d.argtypes = [C.POINTER(trbt_problem_d), i32,
+                                                 C.POINTER(trbt_plan_config),
+                                                 C.POINTER(vp), vp]
+        L.trbt_plan_create_batched_d.restype = i32
+        L.trbt_plan_exec.argtypes = [vp, vp]
+        L.trbt_plan_exec.restype = i32
+        L.trbt_plan_get_config.argtypes = [vp, C.POINTER(trbt_plan_config),
+                                           C.POINTER(C.c_double)]
+        L.trbt_plan_get_config.restype = i32
+        L.trbt_plan_check.argtypes = [vp, C.POINTER(i32)]
+        L.trbt_plan_check.restype = i32
+        L.trbt_plan_destroy.argtypes = [vp]
+        L.trbt_plan_destroy.restype = i32
         L.trbt_strerror.argtypes = [i32]
         L.trbt_strerror.restype = C.c_char_p
         _lib = L
@@ -174,3 +200,103 @@ def back_transform(Z, hh_v, hh_tau, nbw: int, work=None, stream=None):
     if rc:
         raise TrbtError(rc, f.__name__)
     return Z
+
+
+# --------------------------------------------------------------------------
+# Batched plans
+# --------------------------------------------------------------------------
+def trbt_plan_create_batched_d(probs, cfg=None, stream=None):
+    """probs: sequence of trbt_problem_d (or of tuples in its field order).
+    cfg: None (autotune) or trbt_plan_config / (strip_cols, waves, block_stages).
+    Returns (status, plan handle or None)."""
+    arr = (trbt_problem_d * max(len(probs), 1))()
+    for i, p in enumerate(probs):
+        arr[i] = p if isinstance(p, trbt_problem_d) else trbt_problem_d(*p)
+    c = None
+    if cfg is not None:
+        c = cfg if isinstance(cfg, trbt_plan_config) else trbt_plan_config(*cfg)
+    h = C.c_void_p()
+    rc = lib().trbt_plan_create_batched_d(arr if probs else None, len(probs),
+                                          C.byref(c) if c is not None else None, C.byref(h),
+                                          _stream(stream))
+    return rc, (h.value if rc == 0 else None)
+
+
+def trbt_plan_exec(plan, stream=None) -> int:
+    return lib().trbt_plan_exec(plan, _stream(stream))
+
+
+def trbt_plan_get_config(plan):
+    c = trbt_plan_config()
+    ms = C.c_double()
+    rc = lib().trbt_plan_get_config(plan, C.byref(c), C.byref(ms))
+    if rc:
+        raise TrbtError(rc, "trbt_plan_get_config")
+    return (c.strip_cols, c.waves, c.block_stages), ms.value
+
+
+def trbt_plan_check(plan) -> int:
+    f = C.c_int()
+    rc = lib().trbt_plan_check(plan, C.byref(f))
+    if rc:
+        raise TrbtError(rc, "trbt_plan_check")
+    return f.value
+
+
+def trbt_plan_destroy(plan) -> int:
+    return lib().trbt_plan_destroy(plan)
+
+
+class BatchedPlan:
+    """A batched plan over torch tensors.
+
+    problems: list of (Z, hh_v, hh_tau, nbw) with Z an (n, nev) float64
+    column-major view (unit row stride) and hh_v (K, nbw), hh_tau (K,)
+    contiguous float64, all on the current device.  The tensors must stay
+    alive (same storage) for the plan's lifetime; their contents may change
+    between runs."""
+
+    def __init__(self, problems, cfg=None, stream=None):
+        import torch
+        descs = []
+        self._keep = []
+        for Z, hv, ht, nbw in problems:
+            n, nev = Z.shape
+            if nev and n and Z.stride(0) != 1:
+                raise ValueError("Z must be column-major (unit row stride)")
+            for t in (Z, hv, ht):
+                if t.dtype != torch.float64:
+                    raise TypeError("batched plans are real FP64")
+            if not hv.is_contiguous() or not ht.is_contiguous():
+                raise TypeError("hh_v and hh_tau must be contiguous")
+            ldz = Z.stride(1) if nev > 1 else max(n, 1)
+            descs.append(trbt_problem_d(n, nbw, nev, _ptr(hv) if hv.numel() else None,
+                                        _ptr(ht) if ht.numel() else None,
+                                        _ptr(Z) if Z.numel() else None, max(ldz, 1)))
+            self._keep.append((Z, hv, ht))
+        rc, self.handle = trbt_plan_create_batched_d(descs, cfg, stream)
+        if rc:
+            raise TrbtError(rc, "trbt_plan_create_batched_d")
+
+    @property
+    def config(self):
+        return trbt_plan_get_config(self.handle)
+
+    def run(self, stream=None):
+        rc = trbt_plan_exec(self.handle, stream)
+        if rc:
+            raise TrbtError(rc, "trbt_plan_exec")
+
+    def fault(self) -> int:
+        return trbt_plan_check(self.handle)
+
+    def close(self):
+        if self.handle is not None:
+            trbt_plan_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -1,0 +1,682 @@
+// trbt_device.h -- device code shared by the single-problem, batched and
+// adjoint entry points of libtrbt (gfx950).  Internal header: it defines
+// kernels and helpers in an anonymous namespace, so every translation unit
+// that includes it gets its own instantiations.
+//
+//
+// Operation (Yu et al., CPC 2020, Sec. 2.2.2, Eq. 2stage_bkwd1 and
+// Eq. kernel): apply every Householder reflector H_k = I - tau_k v_k v_k^H
+// produced by bulge chasing (Sec. 2.2.1) to every column of Z, in exactly
+// the reverse of the generation order.  Columns are independent; reflectors
+// of one stage touch disjoint rows; from stage s to s-1 the window of every
+// sweep ("slot") moves up by one row (Sec. 3.2, Fig. kernel).
+//
+// Two device paths:
+//
+//  * unblocked ("generic"): one lane per column, every reflector applied
+//    by a dot product and an axpy on the column in global memory, in a
+//    blocked topological order of the reflector DAG.  Any nbw.
+//
+//  * blocked ("tile ring", nbw a multiple of 16, up to 64): the reflectors
+//    of one slot over 16 consecutive stages are merged into one compact-WY
+//    factor  H_a ... H_b = I - V T V^H  (Schreiber & Van Loan); a pack
+//    kernel precomputes, per (slot, 16-stage block), A1 = T V^H and -V in
+//    the register layout of v_mfma_f64_16x16x4_f64.  The main kernel gives
+//    each workgroup a strip of columns; each of its 8 waves owns one slot at
+//    a time and keeps that slot's (nbw+16) x (16*CT) window of Z in
+//    registers while the window slides up 16 rows per block, exchanging one
+//    16-row tile per block with the neighbouring slots through Z (same CU,
+//    workgroup-scope release/acquire on LDS progress counters).  Per block
+//    the update is two small dense products on FP64 MFMA:
+//        Y = A1 * Zwin        (16 x 16CT, K = nbw+16)
+//        Zwin += (-V) * Y     (nbw+16 x 16CT, K = 16)
+//
+// Ordering argument for the blocked path (0-based stage s, slot j, block
+// t = stages n-3-16t .. n-18-16t): reflector (s, j) depends only on (s+1, j)
+// and (s+1, j-1); hence block (t, j) depends on (t-1, j) and (t, j-1).
+// A wave walks its slot's blocks in order, and before block t waits until
+// slot j-1 has finished block t.  Slot j's window at block t is rows
+// [p0, p0+nbw+16) with p0 = s_top-15+j*nbw; its top 16-row tile is exactly
+// the tile slot j-1 retires after block t, and its bottom tile is the one
+// slot j+1 picks up.
+
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <stdint.h>
+#include <string.h>
+
+#include "trbt.h"
+
+namespace {
+
+// --------------------------------------------------------------------------
+// Reflector geometry (Sec. 2.2.1), shared by host validation and kernels.
+// --------------------------------------------------------------------------
+__host__ __device__ inline int64_t sweeps_in_stage(int64_t n, int64_t b, int64_t s)
+{
+    if (n < 3 || b < 2 || s < 0 || s > n - 3) return 0;
+    return (n - s - 2 + b - 1) / b;
+}
+
+// F(M) = sum_{m=1..M} ceil(m/b) = b q(q+1)/2 + r(q+1), M = q b + r
+__host__ __device__ inline int64_t ceil_sum(int64_t M, int64_t b)
+{
+    if (M <= 0) return 0;
+    int64_t q = M / b, r = M % b;
+    return b * q * (q + 1) / 2 + r * (q + 1);
+}
+
+// generation index of reflector (s, 0): sum_{s' < s} ceil((n-s'-2)/b)
+__host__ __device__ inline int64_t stage_offset(int64_t n, int64_t b, int64_t s)
+{
+    if (b < 2 || n < 3) return 0;
+    return ceil_sum(n - 2, b) - ceil_sum(n - 2 - s, b);
+}
+
+__host__ __device__ inline int64_t num_reflectors(int64_t n, int64_t b)
+{
+    return stage_offset(n, b, n - 2);
+}
+
+// --------------------------------------------------------------------------
+// Scalar helpers
+// --------------------------------------------------------------------------
+struct cd {
+    double re, im;
+};
+
+typedef double d4 __attribute__((ext_vector_type(4)));
+
+__device__ inline double conj_mul_re(cd a, cd b) { return a.re * b.re + a.im * b.im; }  // Re(conj(a) b)
+__device__ inline double conj_mul_im(cd a, cd b) { return a.re * b.im - a.im * b.re; }  // Im(conj(a) b)
+
+// ==========================================================================
+// Unblocked kernel: one lane per column.
+// Order: 16-stage blocks from the top stage down; inside a block, slot by
+// slot (ascending), and inside a slot stage by stage (descending).  This is
+// a valid topological order of the reflector DAG for every nbw, and it
+// reuses each slot's rows for 16 consecutive reflectors.
+// ==========================================================================
+__device__ inline void apply_one(double* z, const double* __restrict__ v, double tau, int len)
+{
+    double d = 0.0;
+    for (int i = 0; i < len; ++i) d = fma(v[i], z[i], d);
+    const double a = tau * d;
+    for (int i = 0; i < len; ++i) z[i] = fma(-a, v[i], z[i]);
+}
+
+__device__ inline void apply_one(cd* z, const cd* __restrict__ v, cd tau, int len)
+{
+    double dr = 0.0, di = 0.0;
+    for (int i = 0; i < len; ++i) {
+        const cd vi = v[i], zi = z[i];
+        dr += conj_mul_re(vi, zi);
+        di += conj_mul_im(vi, zi);
+    }
+    const double ar = tau.re * dr - tau.im * di;
+    const double ai = tau.re * di + tau.im * dr;
+    for (int i = 0; i < len; ++i) {
+        const cd vi = v[i];
+        cd zi = z[i];
+        zi.re -= ar * vi.re - ai * vi.im;
+        zi.im -= ar * vi.im + ai * vi.re;
+        z[i] = zi;
+    }
+}
+
+template <typename T>
+__device__ inline void unblocked_column(int64_t n, int nbw, const T* __restrict__ hv,
+                                        const T* __restrict__ ht, T* __restrict__ z)
+{
+    const int64_t nblk = (n - 2 + 15) / 16;
+    for (int64_t t = 0; t < nblk; ++t) {
+        const int64_t stop = n - 3 - 16 * t;
+        const int64_t sbot = stop - 15 > 0 ? stop - 15 : 0;
+        const int64_t J = sweeps_in_stage(n, nbw, sbot);
+        for (int64_t j = 0; j < J; ++j) {
+            for (int64_t s = stop; s >= sbot; --s) {
+                if (j >= sweeps_in_stage(n, nbw, s)) continue;
+                const int64_t k = stage_offset(n, nbw, s) + j;
+                const int64_t r0 = s + 1 + j * nbw;
+                const int len = (int)(n - r0 < nbw ? n - r0 : nbw);
+                apply_one(z + r0, hv + k * nbw, ht[k], len);
+            }
+        }
+    }
+}
+
+template <typename T>
+__global__ __launch_bounds__(64) void k_unblocked(int64_t n, int nbw, int64_t nev,
+                                                  const T* __restrict__ hv,
+                                                  const T* __restrict__ ht, T* __restrict__ Z,
+                                                  int64_t ldz)
+{
+    const int64_t col = (int64_t)blockIdx.x * 64 + threadIdx.x;
+    if (col >= nev) return;
+    unblocked_column(n, nbw, hv, ht, Z + col * ldz);
+}
+
+// ==========================================================================
+// Blocked path
+// ==========================================================================
+constexpr int KB = 16;        // stages per block (one MFMA tile of rows)
+constexpr int WAVES = 8;      // slots in flight per workgroup
+constexpr int HDR_BYTES = 256;
+
+// Blocks of slot j: t = j*(nbw/16) .. nblk-1.  Slot-major numbering.
+__host__ __device__ inline int64_t slot_base(int64_t j, int64_t nblk, int64_t nt1)
+{
+    return j * nblk - nt1 * j * (j - 1) / 2;
+}
+
+__host__ inline int64_t blocked_num_blocks(int64_t n, int nbw)
+{
+    const int64_t J = sweeps_in_stage(n, nbw, 0);
+    const int64_t nblk = (n - 2 + KB - 1) / KB;
+    return slot_base(J, nblk, nbw / KB);
+}
+
+template <int NB, bool CPLX>
+struct Geo {
+    static constexpr int NT = NB / 16 + 1;                // tiles in a window
+    static constexpr int NC = CPLX ? 2 : 1;               // planes (re, im)
+    static constexpr int CHUNK = 64 * NC;                 // doubles per chunk
+    static constexpr int A1_DBL = NT * 4 * CHUNK;         // A1 = T V^H, packed
+    static constexpr int PB = 2 * A1_DBL;                 // doubles per block
+};
+
+// --------------------------------------------------------------------------
+// Pack kernel: one workgroup (256 threads) per (slot, block).
+//   Vt[r][p]  window row r in [0, 16*NT), reflector p in [0,16) in generation
+//             order (p = 15 - m, m = stages below the block's top stage);
+//             reflector p occupies window rows [p+1, p+1+len).
+//   T         forward compact-WY factor (upper triangular):
+//             T[p][p] = tau_p, T[0:p, p] = -tau_p T[0:p,0:p] (Vt[:,0:p]^H v_p)
+//   A1[p][r] = sum_{q>=p} T[p][q] conj(Vt[r][q])
+// Packed for v_mfma_f64_16x16x4_f64 (A operand: lane i+16k holds A[i][k];
+// B operand: lane j+16k holds B[k][j]; accumulator: lane j+16g holds rows
+// g, g+4, g+8, g+12 of column j), chunk (q, u):
+//   A1 chunk lane l: A1[l%16][16q + 4u + l/16]     stored at position 4q+u
+//   -V chunk lane l: -Vt[16q + l%16][4u + l/16]    stored at position
+//                                                  4NT + u*NT + (NT-1-q)
+// i.e. in exactly the order the main kernel consumes them.
+// --------------------------------------------------------------------------
+// pack_block packs block `blk` (slot-major numbering) of one problem into
+// ws (the problem's packed-block array); all 256 threads of the workgroup
+// take part.
+template <int NB, bool CPLX>
+__device__ inline void pack_block(int64_t n, const double* __restrict__ hv,
+                                  const double* __restrict__ ht, double* __restrict__ ws,
+                                  int64_t blk)
+{
+    using G = Geo<NB, CPLX>;
+    constexpr int NT = G::NT, NC = G::NC, R = 16 * NT;
+    __shared__ double Vt[R][16][NC];
+    __shared__ double Gm[16][16][NC];
+    __shared__ double Tm[16][16][NC];
+    __shared__ double tau[16][NC];
+    __shared__ int64_t s_j, s_t;
+
+    const int tid = threadIdx.x;
+    const int64_t nblk = (n - 2 + KB - 1) / KB;
+    const int64_t J = sweeps_in_stage(n, NB, 0);
+    constexpr int64_t nt1 = NB / 16;
+    if (tid == 0) {
+        int64_t lo = 0, hi = J;  // find j with slot_base(j) <= blk < slot_base(j+1)
+        while (hi - lo > 1) {
+            int64_t mid = (lo + hi) / 2;
+            if (slot_base(mid, nblk, nt1) <= blk) lo = mid; else hi = mid;
+        }
+        s_j = lo;
+        s_t = lo * nt1 + (blk - slot_base(lo, nblk, nt1));
+    }
+    __syncthreads();
+    const int64_t j = s_j, t = s_t;
+    const int64_t s_top = n - 3 - KB * t;
+
+    for (int idx = tid; idx < R * 16; idx += 256) {
+        const int r = idx / 16, p = idx % 16;
+        const int64_t s = s_top - 15 + p;
+        double re = 0.0, im = 0.0;
+        if (s >= 0 && s <= n - 3 - j * NB) {
+            const int64_t k = stage_offset(n, NB, s) + j;
+            const int64_t r0 = s + 1 + j * NB;
+            const int len = (int)(n - r0 < NB ? n - r0 : NB);
+            const int e = r - (p + 1);
+            if (e >= 0 && e < len) {
+                re = hv[(k * NB + e) * NC];
+                if (CPLX) im = hv[(k * NB + e) * NC + 1];
+            }
+            if (r == 0) {
+                tau[p][0] = ht[k * NC];
+                if (CPLX) tau[p][NC - 1] = ht[k * NC + 1];
+            }
+        } else if (r == 0) {
+            tau[p][0] = 0.0;
+            if (CPLX) tau[p][NC - 1] = 0.0;
+        }
+        Vt[r][p][0] = re;
+        if (CPLX) Vt[r][p][NC - 1] = im;
+    }
+    __syncthreads();
+    {   // Gram matrix Gm[a][b] = sum_r conj(Vt[r][a]) Vt[r][b]
+        const int a = tid / 16, b = tid % 16;
+        double gr = 0.0, gi = 0.0;
+        for (int r = 0; r < R; ++r) {
+            if (CPLX) {
+                cd x = {Vt[r][a][0], Vt[r][a][NC - 1]}, y = {Vt[r][b][0], Vt[r][b][NC - 1]};
+                gr += conj_mul_re(x, y);
+                gi += conj_mul_im(x, y);
+            } else {
+                gr += Vt[r][a][0] * Vt[r][b][0];
+            }
+        }
+        Gm[a][b][0] = gr;
+        if (CPLX) Gm[a][b][NC - 1] = gi;
+        Tm[a][b][0] = (a == b) ? tau[a][0] : 0.0;
+        if (CPLX) Tm[a][b][NC - 1] = (a == b) ? tau[a][NC - 1] : 0.0;
+    }
+    __syncthreads();
+    for (int q = 1; q < 16; ++q) {   // column q of T from columns 0..q-1
+        if (tid < q) {
+            const int p = tid;
+            double wr = 0.0, wi = 0.0;   // w = sum_{i=p}^{q-1} T[p][i] Gm[i][q]
+            for (int i = p; i < q; ++i) {
+                const double tr = Tm[p][i][0], gr = Gm[i][q][0];
+                if (CPLX) {
+                    const double ti = Tm[p][i][NC - 1], gi = Gm[i][q][NC - 1];
+                    wr += tr * gr - ti * gi;
+                    wi += tr * gi + ti * gr;
+                } else {
+                    wr += tr * gr;
+                }
+            }
+            const double ur = tau[q][0], ui = CPLX ? tau[q][NC - 1] : 0.0;
+            Tm[p][q][0] = -(ur * wr - ui * wi);
+            if (CPLX) Tm[p][q][NC - 1] = -(ur * wi + ui * wr);
+        }
+        __syncthreads();
+    }
+    // A1 chunks and -V chunks
+    double* out = ws + (size_t)blk * G::PB;
+    for (int idx = tid; idx < NT * 4 * 64; idx += 256) {
+        const int lane = idx % 64, qu = idx / 64, q = qu / 4, u = qu % 4;
+        {   // A1[p][r] = sum_{q' >= p} T[p][q'] conj(Vt[r][q'])
+            const int p = lane % 16, r = 16 * q + 4 * u + lane / 16;
+            double ar = 0.0, ai = 0.0;
+            for (int c = p; c < 16; ++c) {
+                const double tr = Tm[p][c][0], vr = Vt[r][c][0];
+                if (CPLX) {
+                    const double ti = Tm[p][c][NC - 1], vi = -Vt[r][c][NC - 1];
+                    ar += tr * vr - ti * vi;
+                    ai += tr * vi + ti * vr;
+                } else {
+                    ar += tr * vr;
+                }
+            }
+            out[qu * G::CHUNK + lane] = ar;
+            if (CPLX) out[qu * G::CHUNK + 64 + lane] = ai;
+        }
+        {   // -V chunks in the order the main kernel reads them: u ascending,
+            // and within each u the tiles from the bottom of the window up
+            const int r = 16 * q + lane % 16, p = 4 * u + lane / 16;
+            const int pos = u * NT + (NT - 1 - q);
+            out[G::A1_DBL + pos * G::CHUNK + lane] = -Vt[r][p][0];
+            if (CPLX) out[G::A1_DBL + pos * G::CHUNK + 64 + lane] = -Vt[r][p][NC - 1];
+        }
+    }
+}
+
+template <int NB, bool CPLX>
+__global__ __launch_bounds__(256) void k_pack(int64_t n, const double* __restrict__ hv,
+                                              const double* __restrict__ ht,
+                                              double* __restrict__ ws)
+{
+    pack_block<NB, CPLX>(n, hv, ht, ws, blockIdx.x);
+}
+
+// --------------------------------------------------------------------------
+// Main blocked kernel.
+// Register tile (accumulator layout of v_mfma_f64_16x16x4_f64, checked on
+// gfx950): lane l holds rows l/16 + 4e (e = 0..3) of column l%16.  A K-chunk
+// (q, u) of the window is the 4 consecutive rows 16q + 4u + {0..3}: its B
+// operand in lane l is element u of tile q, so the Z window is an MFMA
+// operand without any data movement.  Likewise element u of the Y tile is
+// the B operand for the reflectors 4u + {0..3}.
+// --------------------------------------------------------------------------
+template <bool CPLX>
+struct Tile;
+template <>
+struct Tile<false> {
+    d4 re;
+};
+template <>
+struct Tile<true> {
+    d4 re, im;
+};
+
+__device__ inline d4 mfma(double a, double b, d4 c)
+{
+    return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+}
+
+typedef double d2 __attribute__((ext_vector_type(2)));
+
+// MFMA with the FP64 negate modifiers of gfx950 (bit 0 negates A, bit 1 B).
+template <int NEG>
+__device__ inline d4 mfma_n(double a, double b, d4 c)
+{
+    return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, NEG);
+}
+
+// Tile load.  Interior tiles (all rows inside the matrix, whole strip inside
+// nev: a wave-uniform test) load directly; edge tiles read a clamped, valid
+// address and zero what lies outside, so all loads issue back to back.
+template <bool CPLX>
+__device__ inline void load_tile(Tile<CPLX>& t, const double* __restrict__ Z, int64_t ldz,
+                                 int64_t n, int64_t nev, int64_t row0, int64_t col,
+                                 bool interior)
+{
+    if (interior) {
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+            const int64_t r = row0 + 4 * e;
+            if constexpr (CPLX) {
+                const d2 x = *(const d2*)(Z + 2 * (col * ldz + r));
+                t.re[e] = x[0];
+                t.im[e] = x[1];
+            } else {
+                t.re[e] = Z[col * ldz + r];
+            }
+        }
+        return;
+    }
+    const bool colok = col < nev;
+    const int64_t cc = colok ? col : nev - 1;
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+        const int64_t r = row0 + 4 * e;
+        const bool ok = colok && r >= 0 && r < n;
+        const int64_t rr = r < 0 ? 0 : (r >= n ? n - 1 : r);
+        if constexpr (CPLX) {
+            const d2 x = *(const d2*)(Z + 2 * (cc * ldz + rr));
+            t.re[e] = ok ? x[0] : 0.0;
+            t.im[e] = ok ? x[1] : 0.0;
+        } else {
+            const double x = Z[cc * ldz + rr];
+            t.re[e] = ok ? x : 0.0;
+        }
+    }
+}
+
+template <bool CPLX>
+__device__ inline void store_tile(const Tile<CPLX>& t, double* __restrict__ Z, int64_t ldz,
+                                  int64_t n, int64_t nev, int64_t row0, int64_t col)
+{
+    if (col >= nev) return;
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+        const int64_t r = row0 + 4 * e;
+        if (r >= 0 && r < n) {
+            if constexpr (CPLX) {
+                *(d2*)(Z + 2 * (col * ldz + r)) = d2{t.re[e], t.im[e]};
+            } else {
+                Z[col * ldz + r] = t.re[e];
+            }
+        }
+    }
+}
+
+// Spin (with s_sleep) until prog[idx] >= need.  A bounded wait: on the
+// never-expected timeout the wave flags the error word and gives up.
+__device__ inline bool wait_progress(int* prog, int idx, int need, unsigned* err, int lane)
+{
+    unsigned spins = 0;
+    while (__hip_atomic_load(&prog[idx], __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_WORKGROUP) < need) {
+        __builtin_amdgcn_s_sleep(2);
+        if (++spins > (1u << 26)) {
+            if (lane == 0) atomicOr(err, 1u);
+            return false;
+        }
+    }
+    return true;
+}
+
+// Operand ring depth (chunks loaded ahead of use).  The ring position of a
+// chunk is its index in the block's stream modulo D, and the ring runs on
+// into the next block, so D must divide the chunk count per block.
+template <int NB, bool CPLX>
+__host__ __device__ constexpr int ring_depth()
+{
+    return CPLX ? 8 : 4 * Geo<NB, CPLX>::NT;
+}
+
+template <bool CPLX, int D>
+__device__ inline void load_chunk(const double* __restrict__ blkp, int c, int lane,
+                                  double (&re)[D], double (&im)[D], int slot)
+{
+    constexpr int CH = CPLX ? 128 : 64;
+    const double* p = blkp + c * CH;
+    re[slot] = p[lane];
+    if constexpr (CPLX) im[slot] = p[64 + lane];
+}
+
+// Main blocked kernel.  Per block the operand stream is consumed in order:
+//   chunks 0 .. 4NT-1       A1 chunk (q, u) = (c/4, c%4):   Y += A1 * Zwin
+//   chunks 4NT .. 8NT-1     -V chunk (u, q), u ascending, q descending:
+//                           Zwin += (-V) * Y
+// During the last u pass (u = 3) each tile's final MFMA writes its result
+// one tile lower in the register window, so the slide of the window by one
+// tile costs no data movement; the bottom tile leaves as `zret`.
+//
+// blocked_strip runs the whole back-transformation of column strip `strip`
+// (columns 16*CT*strip ..) with the NW waves of the calling workgroup; wsb
+// is the problem's packed-block array, prog the workgroup's LDS progress
+// array, all zero on entry.  On the (never expected) time-out of a progress
+// wait a wave sets *err and leaves.
+template <int NB, int CT, bool CPLX, int D, int NW>
+__device__ inline void blocked_strip(int64_t n, int64_t nev, const double* __restrict__ wsb,
+                                     double* __restrict__ Z, int64_t ldz,
+                                     unsigned* __restrict__ err, int64_t strip, int* prog)
+{
+    using G = Geo<NB, CPLX>;
+    constexpr int NT = G::NT;
+    constexpr int NCH = 8 * NT;            // operand chunks per block
+    static_assert(NCH % D == 0, "ring depth must divide the chunks per block");
+    constexpr int64_t nt1 = NB / 16;
+
+    const int lane = threadIdx.x & 63;
+    const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+
+    const int64_t nblk = (n - 2 + KB - 1) / KB;
+    const int64_t J = sweeps_in_stage(n, NB, 0);
+    const int64_t col_base = strip * 16 * CT + (lane & 15);
+    const bool cols_inside = (strip + 1) * 16 * CT <= nev;
+    const int rsub = lane >> 4;
+    const int wprev = (w + NW - 1) % NW;
+
+    Tile<CPLX> zt[NT][CT];
+    double ring_re[D], ring_im[D];
+
+    for (int64_t j = w; j < J; j += NW) {
+        const int64_t t0 = j * nt1;
+        const double* __restrict__ blkp = wsb + (size_t)slot_base(j, nblk, nt1) * G::PB;
+        const int need0 = (int)((j - 1) * (nblk + 1));   // + t + 1: slot j-1 done block t
+        if (j > 0 && !wait_progress(prog, wprev, need0 + (int)t0 + 1, err, lane)) return;
+        int64_t p0 = n - 3 - KB * t0 - 15 + j * NB;
+#pragma unroll
+        for (int q = 0; q < NT; ++q) {
+            const bool inside = cols_inside && p0 + 16 * q >= 0 && p0 + 16 * q + 16 <= n;
+#pragma unroll
+            for (int c = 0; c < CT; ++c)
+                load_tile<CPLX>(zt[q][c], Z, ldz, n, nev, p0 + 16 * q + rsub,
+                                col_base + 16 * c, inside);
+        }
+#pragma unroll
+        for (int c = 0; c < D; ++c) load_chunk<CPLX, D>(blkp, c, lane, ring_re, ring_im, c);
+
+        for (int64_t t = t0; t < nblk; ++t, blkp += G::PB, p0 -= KB) {
+            const bool has_next = t + 1 < nblk;
+            // the top tile of the next block: slot j-1 must have retired it
+            Tile<CPLX> znext[CT];
+            if (has_next) {
+                if (j > 0 && !wait_progress(prog, wprev, need0 + (int)t + 2, err, lane)) return;
+                const bool inside = cols_inside && p0 - 16 >= 0 && p0 <= n;
+#pragma unroll
+                for (int c = 0; c < CT; ++c)
+                    load_tile<CPLX>(znext[c], Z, ldz, n, nev, p0 - 16 + rsub, col_base + 16 * c,
+                                    inside);
+            }
+
+            Tile<CPLX> y[2][CT];   // two partial sums: more independent MFMA chains
+#pragma unroll
+            for (int h = 0; h < 2; ++h)
+#pragma unroll
+                for (int c = 0; c < CT; ++c) {
+                    y[h][c].re = d4{0.0, 0.0, 0.0, 0.0};
+                    if constexpr (CPLX) y[h][c].im = d4{0.0, 0.0, 0.0, 0.0};
+                }
+            Tile<CPLX> zsh[NT + 1][CT];   // window after the slide; zsh[NT] retires
+
+#pragma unroll
+            for (int c = 0; c < NCH; ++c) {
+                const int slot = c % D;
+                const double ar = ring_re[slot];
+                const double ai = CPLX ? ring_im[slot] : 0.0;
+                if (c + D < NCH)
+                    load_chunk<CPLX, D>(blkp, c + D, lane, ring_re, ring_im, slot);
+                else if (has_next)
+                    load_chunk<CPLX, D>(blkp + G::PB, c + D - NCH, lane, ring_re, ring_im, slot);
+                if (c < 4 * NT) {
+                    // Y += A1(:, chunk) * Zwin(chunk, :)
+                    const int q = c / 4, u = c % 4, h = q & 1;
+#pragma unroll
+                    for (int cc = 0; cc < CT; ++cc) {
+                        if constexpr (CPLX) {
+                            y[h][cc].re = mfma_n<0>(ar, zt[q][cc].re[u], y[h][cc].re);
+                            y[h][cc].im = mfma_n<0>(ar, zt[q][cc].im[u], y[h][cc].im);
+                            y[h][cc].re = mfma_n<1>(ai, zt[q][cc].im[u], y[h][cc].re);
+                            y[h][cc].im = mfma_n<0>(ai, zt[q][cc].re[u], y[h][cc].im);
+                        } else {
+                            y[h][cc].re = mfma_n<0>(ar, zt[q][cc].re[u], y[h][cc].re);
+                        }
+                    }
+                    if (c == 4 * NT - 1) {
+#pragma unroll
+                        for (int cc = 0; cc < CT; ++cc) {
+                            y[0][cc].re += y[1][cc].re;
+                            if constexpr (CPLX) y[0][cc].im += y[1][cc].im;
+                        }
+                    }
+                } else {
+                    // Zwin(tile q, :) += (-V)(tile q, chunk u) * Y(chunk u, :)
+                    const int c2 = c - 4 * NT, u = c2 / NT, q = NT - 1 - c2 % NT;
+#pragma unroll
+                    for (int cc = 0; cc < CT; ++cc) {
+                        const Tile<CPLX>& src = zt[q][cc];
+                        Tile<CPLX>& dst = (u == 3) ? zsh[q + 1][cc] : zt[q][cc];
+                        if constexpr (CPLX) {
+                            const d4 re = mfma_n<0>(ar, y[0][cc].re[u], src.re);
+                            const d4 im = mfma_n<0>(ar, y[0][cc].im[u], src.im);
+                            dst.re = mfma_n<2>(ai, y[0][cc].im[u], re);
+                            dst.im = mfma_n<0>(ai, y[0][cc].re[u], im);
+                        } else {
+                            dst.re = mfma_n<0>(ar, y[0][cc].re[u], src.re);
+                        }
+                    }
+                }
+            }
+
+            if (has_next) {
+#pragma unroll
+                for (int c = 0; c < CT; ++c)
+                    store_tile<CPLX>(zsh[NT][c], Z, ldz, n, nev, p0 + 16 * (NT - 1) + rsub,
+                                     col_base + 16 * c);
+            } else {
+#pragma unroll
+                for (int q = 0; q < NT; ++q)
+#pragma unroll
+                    for (int c = 0; c < CT; ++c)
+                        store_tile<CPLX>(zsh[q + 1][c], Z, ldz, n, nev, p0 + 16 * q + rsub,
+                                         col_base + 16 * c);
+            }
+            __hip_atomic_store(&prog[w], (int)(j * (nblk + 1) + t + 1), __ATOMIC_RELEASE,
+                               __HIP_MEMORY_SCOPE_WORKGROUP);
+            if (has_next) {
+#pragma unroll
+                for (int q = 1; q < NT; ++q)
+#pragma unroll
+                    for (int c = 0; c < CT; ++c) zt[q][c] = zsh[q][c];
+#pragma unroll
+                for (int c = 0; c < CT; ++c) zt[0][c] = znext[c];
+            }
+        }
+    }
+}
+
+template <int NB, int CT, bool CPLX, int D, int NW>
+__global__ __launch_bounds__(64 * NW) void k_blocked(int64_t n, int64_t nev,
+                                                     const double* __restrict__ ws,
+                                                     double* __restrict__ Z, int64_t ldz,
+                                                     unsigned* __restrict__ err)
+{
+    __shared__ int prog[NW];
+    if (threadIdx.x < NW) prog[threadIdx.x] = 0;
+    __syncthreads();
+    blocked_strip<NB, CT, CPLX, D, NW>(n, nev, ws + HDR_BYTES / sizeof(double), Z, ldz, err,
+                                       blockIdx.x, prog);
+}
+
+__global__ void k_zero_words(unsigned* p, int count)
+{
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < count) p[i] = 0u;
+}
+
+// --------------------------------------------------------------------------
+// Host-side helpers shared by the entry points
+// --------------------------------------------------------------------------
+inline int check_device()
+{
+    // The device capability is looked up once per device id and cached.
+    static int cached[64];   // 0 unknown, 1 gfx950, 2 other
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return TRBT_ERR_HIP;
+    if (dev >= 0 && dev < 64 && cached[dev]) return cached[dev] == 1 ? TRBT_SUCCESS : TRBT_ERR_DEVICE;
+    hipDeviceProp_t prop;
+    if (hipGetDeviceProperties(&prop, dev) != hipSuccess) return TRBT_ERR_HIP;
+    const int ok = strncmp(prop.gcnArchName, "gfx950", 6) == 0;
+    if (dev >= 0 && dev < 64) cached[dev] = ok ? 1 : 2;
+    return ok ? TRBT_SUCCESS : TRBT_ERR_DEVICE;
+}
+
+inline bool blocked_eligible(int nbw) { return nbw == 16 || nbw == 32 || nbw == 48 || nbw == 64; }
+
+inline size_t blocked_bytes(int64_t n, int nbw, bool cplx)
+{
+    const int nt = nbw / 16 + 1;
+    const size_t pb = (size_t)2 * nt * 4 * 64 * (cplx ? 2 : 1);
+    return HDR_BYTES + (size_t)blocked_num_blocks(n, nbw) * pb * sizeof(double);
+}
+
+inline int validate(int64_t n, int nbw, int64_t nev, const void* hv, const void* ht,
+                    const void* Z, int64_t ldz, const void* work, size_t work_bytes)
+{
+    if (n < 0) return -1;
+    if (nbw < 1 || nbw > TRBT_NBW_MAX) return -2;
+    if (nev < 0 || nev > n) return -3;
+    const int64_t K = num_reflectors(n, nbw);
+    const bool active = K > 0 && nev > 0;
+    if (active && !hv) return -4;
+    if (active && !ht) return -5;
+    if (nev > 0 && n > 0 && !Z) return -6;
+    if (ldz < (n > 1 ? n : 1)) return -7;
+    if (work && ((uintptr_t)work % TRBT_WORK_ALIGN)) return -8;
+    if (work_bytes && !work) return -8;
+    (void)work_bytes;
+    return TRBT_SUCCESS;
+}
+
+}  // namespace

@@ -113,3 +113,32 @@ def test_strerror(T):
     assert "gfx950" in T.trbt_strerror(-100)
     assert "workspace" in T.trbt_strerror(-101)
     assert "argument" in T.trbt_strerror(-3)
+
+
+def test_plan_validation_codes(T):
+    """Batched plan creation rejects bad arguments on the host, before any
+    HIP call: -1 probs, -2 count, -3 configuration, -4 plan, and
+    TRBT_ERR_PROBLEM(i) = -(1000 + i) for the first bad descriptor."""
+    import ctypes as C
+    lib = T.lib()
+    good = T.trbt_problem_d(100, 32, 10, FAKE, FAKE, FAKE, 100)
+    arr = (T.trbt_problem_d * 3)(good, good, good)
+    h = C.c_void_p()
+    assert lib.trbt_plan_create_batched_d(None, 2, None, C.byref(h), None) == -1
+    assert lib.trbt_plan_create_batched_d(arr, -1, None, C.byref(h), None) == -2
+    for bad in [(8, 8, 16), (16, 6, 16), (16, 8, 4), (48, 8, 16)]:
+        cfg = T.trbt_plan_config(*bad)
+        assert lib.trbt_plan_create_batched_d(arr, 3, C.byref(cfg), C.byref(h), None) == -3
+    assert lib.trbt_plan_create_batched_d(arr, 3, None, None, None) == -4
+    for i, bad in [(0, dict(n=-1)), (1, dict(nev=101)), (2, dict(ldz=50)),
+                   (1, dict(hh_v=None)), (2, dict(nbw=0)), (0, dict(Z=None))]:
+        fields = dict(n=100, nbw=32, nev=10, hh_v=FAKE, hh_tau=FAKE, Z=FAKE, ldz=100)
+        fields.update(bad)
+        a = (T.trbt_problem_d * 3)(good, good, good)
+        a[i] = T.trbt_problem_d(**fields)
+        h = C.c_void_p(1234)
+        assert lib.trbt_plan_create_batched_d(a, 3, None, C.byref(h), None) == -1000 - i
+        assert h.value is None
+    assert lib.trbt_plan_exec(None, None) == -1
+    assert lib.trbt_plan_get_config(None, None, None) == -1
+    assert lib.trbt_plan_destroy(None) == 0
