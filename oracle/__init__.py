@@ -58,6 +58,7 @@ def lib():
                                            C.c_void_p, _i64]
         L.orc_apply_q_z.argtypes = [_i64, _i64, _i64, _i64, C.c_void_p, C.c_void_p,
                                     C.c_void_p, _i64]
+        L.orc_adjoint_d.argtypes = [_i64, _i64, _i64, _dp, _dp, _dp, _i64, _dp, _i64, _dp, _dp]
         L.orc_tridi_ql.argtypes = [_i64, _dp, _dp, _dp, _i64]
         L.orc_jacobi_d.argtypes = [_i64, _dp, _dp, _dp]
         L.orc_num_threads.restype = C.c_int
@@ -190,6 +191,27 @@ def apply_q(Z: np.ndarray, hh_v, hh_tau, nbw: int) -> np.ndarray:
     ht = np.ascontiguousarray(hh_tau, dtype=np.complex128)
     _check(lib().orc_apply_q_z(n, nbw, 0, nev, _v(hv), _v(ht), _v(Y), max(n, 1)), "apply_q")
     return Y if np.iscomplexobj(Z) else Y.real.copy(order="F")
+
+
+def adjoint(Z_in: np.ndarray, G: np.ndarray, hh_v: np.ndarray, hh_tau: np.ndarray, nbw: int):
+    """Reverse-mode derivative of the real back-transformation
+    Z_out = H_0 ... H_{K-1} Z_in (Eq. 2stage_bkwd1, real reflectors).
+    G = dL/dZ_out (n, nev).  Returns (dL/dZ_in, dL/dv (K, nbw), dL/dtau (K,))."""
+    Zi = np.array(Z_in, dtype=np.float64, order="F", copy=True)
+    Gi = np.array(G, dtype=np.float64, order="F", copy=True)
+    n, nev = Zi.shape
+    K = num_reflectors(n, nbw)
+    hv = np.ascontiguousarray(hh_v, dtype=np.float64)
+    ht = np.ascontiguousarray(hh_tau, dtype=np.float64)
+    if hv.size == 0:
+        hv = np.zeros((1, nbw))
+        ht = np.zeros(1)
+    dv = np.zeros((max(K, 1), nbw))
+    dt = np.zeros(max(K, 1))
+    ld = max(n, 1)
+    _check(lib().orc_adjoint_d(n, nbw, nev, _p(hv), _p(ht), _p(Zi), ld, _p(Gi), ld, _p(dv),
+                               _p(dt)), "adjoint")
+    return Gi, dv[:K], dt[:K]
 
 
 # --------------------------------------------------------------------------

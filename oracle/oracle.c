@@ -455,6 +455,102 @@ int orc_apply_q_z(int64_t n, int64_t b, int64_t c0, int64_t c1, const zc *hh_v,
 }
 
 /* ------------------------------------------------------------------------
+ * Adjoint (reverse-mode derivative) of the real back-transformation
+ *     Z_out = H_0 H_1 ... H_{K-1} Z_in,   H_k = I - tau_k v_k v_k^T
+ * (Eq. 2stage_bkwd1 with real reflectors).  Given G = dL/dZ_out, return
+ * dL/dZ_in (in G), dL/dv (K x b, zero beyond len) and dL/dtau (K).
+ *
+ * Plain reverse mode, one column at a time (columns are independent in Z;
+ * only dv and dtau sum over them):
+ *   forward  k = K-1 .. 0: record the rows [r0, r0+len) of the column as
+ *            they enter H_k (the tape), then apply H_k;
+ *   reverse  k = 0 .. K-1, with z = tape entry k, g = current gradient rows:
+ *              gk = v.g,  wk = v.z
+ *              dtau_k += -gk wk
+ *              dv_k   += -tau_k (wk g + gk z)
+ *              g      <- g - tau_k gk v        (= H_k^T g)
+ * Derivation: the column update z' = z - tau v (v.z) has
+ *   dL/dz = g - tau v (v.g),  dL/dtau = -(v.z)(v.g),
+ *   dL/dv = -tau ((v.z) g + (v.g) z).
+ * Per-thread accumulators are summed in thread order at the end.
+ * ---------------------------------------------------------------------- */
+int orc_adjoint_d(int64_t n, int64_t b, int64_t nev, const double *hh_v,
+                  const double *hh_tau, const double *Zin, int64_t ldz, double *G,
+                  int64_t ldg, double *dv, double *dtau)
+{
+    if (n < 0 || b < 1 || nev < 0 || ldz < (n > 1 ? n : 1) || ldg < (n > 1 ? n : 1))
+        return ORC_EARG;
+    const int64_t K = orc_num_reflectors(n, b);
+    for (int64_t i = 0; i < K * b; ++i) dv[i] = 0.0;
+    for (int64_t k = 0; k < K; ++k) dtau[k] = 0.0;
+    if (K == 0 || nev == 0) return ORC_OK;
+    int64_t *r0 = malloc(sizeof(int64_t) * K);
+    int64_t *ln = malloc(sizeof(int64_t) * K);
+    int64_t *toff = malloc(sizeof(int64_t) * (K + 1));
+    if (!r0 || !ln || !toff) { free(r0); free(ln); free(toff); return ORC_ENOMEM; }
+    orc_reflector_table(n, b, NULL, NULL, r0, ln);
+    toff[0] = 0;
+    for (int64_t k = 0; k < K; ++k) toff[k + 1] = toff[k] + ln[k];
+    const int nt = omp_get_max_threads();
+    double *acc_v = calloc((size_t)nt * K * b, sizeof(double));
+    double *acc_t = calloc((size_t)nt * K, sizeof(double));
+    int fail = !acc_v || !acc_t;
+    if (!fail) {
+#pragma omp parallel num_threads(nt)
+        {
+            const int me = omp_get_thread_num();
+            double *av = acc_v + (size_t)me * K * b, *at = acc_t + (size_t)me * K;
+            double *tape = malloc(sizeof(double) * toff[K]);
+            double *z = malloc(sizeof(double) * (n > 0 ? n : 1));
+            if (!tape || !z) {
+#pragma omp atomic write
+                fail = 1;
+            } else {
+#pragma omp for schedule(static)
+                for (int64_t c = 0; c < nev; ++c) {
+                    for (int64_t i = 0; i < n; ++i) z[i] = Zin[c * ldz + i];
+                    for (int64_t k = K - 1; k >= 0; --k) {
+                        const double *v = hh_v + k * b;
+                        double *zz = z + r0[k];
+                        double d = 0.0;
+                        for (int64_t i = 0; i < ln[k]; ++i) {
+                            tape[toff[k] + i] = zz[i];
+                            d += v[i] * zz[i];
+                        }
+                        const double a = hh_tau[k] * d;
+                        for (int64_t i = 0; i < ln[k]; ++i) zz[i] -= a * v[i];
+                    }
+                    double *g = G + c * ldg;
+                    for (int64_t k = 0; k < K; ++k) {
+                        const double *v = hh_v + k * b, *zk = tape + toff[k];
+                        double *gg = g + r0[k];
+                        double gk = 0.0, wk = 0.0;
+                        for (int64_t i = 0; i < ln[k]; ++i) {
+                            gk += v[i] * gg[i];
+                            wk += v[i] * zk[i];
+                        }
+                        const double t = hh_tau[k];
+                        at[k] -= gk * wk;
+                        for (int64_t i = 0; i < ln[k]; ++i) av[k * b + i] -= t * (wk * gg[i] + gk * zk[i]);
+                        for (int64_t i = 0; i < ln[k]; ++i) gg[i] -= t * gk * v[i];
+                    }
+                }
+            }
+            free(tape);
+            free(z);
+        }
+    }
+    if (!fail) {
+        for (int th = 0; th < nt; ++th) {
+            for (int64_t i = 0; i < K * b; ++i) dv[i] += acc_v[(size_t)th * K * b + i];
+            for (int64_t k = 0; k < K; ++k) dtau[k] += acc_t[(size_t)th * K + k];
+        }
+    }
+    free(acc_v); free(acc_t); free(r0); free(ln); free(toff);
+    return fail ? ORC_ENOMEM : ORC_OK;
+}
+
+/* ------------------------------------------------------------------------
  * Symmetric tridiagonal eigensolver, Eq. 2stage_solve, by the implicit QL
  * algorithm with Wilkinson shift (Golub & Van Loan, Sec. 8.3; the paper
  * itself uses divide and conquer, which reaches the same eigenpairs).
