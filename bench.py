@@ -158,6 +158,130 @@ def batched_leg(steps: int, warmup: int):
     }
 
 
+def plain_adjoint(Z, G, V, tau, nbw):
+    """The plain form of the differentiation workload: eager PyTorch autograd
+    through a per-stage implementation (one batched gather / bmm / update /
+    index_copy per stage, all slots of the stage at once), with
+    torch.utils.checkpoint over 16-stage segments so that memory stays
+    bounded.  Returns (dL/dZ_in, dL/dv, dL/dtau) for L = <G, Z_out>."""
+    import torch
+    from torch.utils.checkpoint import checkpoint
+    dev = Z.device
+    n, nev = Z.shape
+    import paper_2002_10991_amd as T
+    off = T.trbt_stage_offsets(n, nbw)
+    # per stage: padded row indices (S_s, nbw); row n is a zero dummy row
+    idx, lens = [], []
+    for s in range(n - 2):
+        S = int(off[s + 1] - off[s])
+        r0 = s + 1 + nbw * np.arange(S)
+        rows = r0[:, None] + np.arange(nbw)[None, :]
+        rows[rows >= n] = n
+        idx.append(torch.from_numpy(rows).to(dev))
+    Zin = Z.detach().clone().requires_grad_(True)
+    Vg = V.detach().clone().requires_grad_(True)
+    tg = tau.detach().clone().requires_grad_(True)
+
+    def stage(Zp, s):
+        rows = idx[s]
+        a, b = int(off[s]), int(off[s + 1])
+        v = Vg[a:b]                                       # (S, nbw), zero beyond len
+        W = Zp[rows.reshape(-1)].reshape(rows.shape[0], nbw, nev)
+        d = torch.bmm(v.unsqueeze(1), W)                  # (S, 1, nev)
+        W2 = W - tg[a:b, None, None] * v.unsqueeze(2) * d
+        return Zp.index_copy(0, rows.reshape(-1), W2.reshape(-1, nev))
+
+    def segment(Zp, s_hi, s_lo):
+        for s in range(s_hi, s_lo - 1, -1):
+            Zp = stage(Zp, s)
+        return Zp
+
+    Zp = torch.cat([Zin, torch.zeros(1, nev, dtype=Z.dtype, device=dev)], 0)
+    s = n - 3
+    while s >= 0:
+        lo = max(s - 15, 0)
+        Zp = checkpoint(segment, Zp, s, lo, use_reentrant=False)
+        s = lo - 1
+    loss = (Zp[:n] * G).sum()
+    loss.backward()
+    return Zin.grad, Vg.grad, tg.grad
+
+
+def adjoint_leg(warmup: int):
+    """Forward plus hand-written adjoint (checkpoints every 16 stages) against
+    the plain form, on the differentiation workload: real, n=4096, nbw=64,
+    nev=2048, G ~ N(0,1) (seed 2005)."""
+    import torch
+    import paper_2002_10991_amd as T
+    import synth
+    dev = torch.device("cuda:0")
+    n, nbw, nev = 4096, 64, 2048
+    lengths = synth.reflector_lengths(n, nbw)
+    V, tau = synth.unitary_reflectors(lengths, nbw, 1005, "d")
+    Zh = synth.gaussian(n, nev, 1006, "d")
+    Gh = synth.gaussian(n, nev, 2005, "d")
+    L = int(lengths.sum())
+    Vd, td = torch.from_numpy(V).to(dev), torch.from_numpy(tau).to(dev)
+    Zbuf = torch.from_numpy(np.ascontiguousarray(Zh.T)).to(dev)    # (nev, n): column-major Z
+    Gsrc = torch.from_numpy(np.ascontiguousarray(Gh.T)).to(dev)
+    Obuf, Gbuf = torch.empty_like(Zbuf), torch.empty_like(Gsrc)
+    K = len(tau)
+    dv = torch.empty(K, nbw, dtype=torch.float64, device=dev)
+    dt = torch.empty(K, dtype=torch.float64, device=dev)
+    fw = T.alloc_workspace(n, nbw, nev, False, dev)
+    fwb = fw.numel()
+    nb = T.trbt_adjoint_workspace_bytes_d(n, nbw, nev)
+    abuf = torch.empty(nb + T.TRBT_WORK_ALIGN, dtype=torch.uint8, device=dev)
+    aw = abuf[(-abuf.data_ptr()) % T.TRBT_WORK_ALIGN:][:nb]
+    stream = torch.cuda.current_stream()
+
+    def ours():
+        Obuf.copy_(Zbuf)
+        Gbuf.copy_(Gsrc)
+        rc = T.trans_ev_tridi_to_band_d(n, nbw, nev, Vd, td, Obuf, n, fw, fwb, stream)
+        rc = rc or T.trans_ev_tridi_to_band_adjoint_d(n, nbw, nev, Vd, td, Zbuf, n, Gbuf, n, dv,
+                                                      dt, 16, aw, nb, stream)
+        if rc:
+            raise T.TrbtError(rc, "adjoint leg")
+
+    for _ in range(max(warmup, 1)):
+        ours()
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    reps = 3
+    e0.record(stream)
+    for _ in range(reps):
+        ours()
+    e1.record(stream)
+    torch.cuda.synchronize()
+    ours_ms = e0.elapsed_time(e1) / reps
+    if int(aw[:4].view(torch.int32).cpu()[0]):
+        raise RuntimeError("adjoint: device wait-timeout flag set")
+    log(f"C5 forward + adjoint: {ours_ms:.2f} ms")
+    t = time.perf_counter()
+    pz, pv, pt = plain_adjoint(Zbuf.t(), Gsrc.t(), Vd, td, nbw)
+    torch.cuda.synchronize()
+    plain_ms = (time.perf_counter() - t) * 1e3
+    log(f"C5 plain form: {plain_ms:.1f} ms")
+
+    def rel(a, b):
+        return float(torch.linalg.norm(a - b) / torch.linalg.norm(b))
+
+    flops = 18 * L * nev
+    return {
+        "workload": "C5: real, n=4096, nbw=64, nev=2048, forward + adjoint, checkpoints every "
+                    "16 stages, G ~ N(0,1) seed 2005",
+        "flops_counted": flops,
+        "ours_ms": round(ours_ms, 3), "plain_ms": round(plain_ms, 1),
+        "ours_tflops": round(flops / ours_ms / 1e9, 4),
+        "speedup_vs_plain": round(plain_ms / ours_ms, 2),
+        "plain_form": "eager PyTorch autograd, one batched op per stage, torch.utils.checkpoint "
+                      "every 16 stages",
+        "max_rel_diff_vs_plain": {"dZ_in": rel(Gbuf.t(), pz), "dv": rel(dv, pv),
+                                  "dtau": rel(dt, pt)},
+    }
+
+
 def committed_traffic(workload: str):
     """HBM bytes per launch of the apply kernel from the committed rocprofv3
     counter summary, if it was taken on the current kernel source; else None."""
@@ -187,6 +311,10 @@ def main():
                     help="skip the batched-vs-looped comparison on the 64-problem workload")
     ap.add_argument("--batched-only", action="store_true",
                     help="run only the batched-vs-looped comparison and print its JSON")
+    ap.add_argument("--no-adjoint", action="store_true",
+                    help="skip the adjoint-vs-plain comparison on the differentiation workload")
+    ap.add_argument("--adjoint-only", action="store_true",
+                    help="run only the adjoint-vs-plain comparison and print its JSON")
     ap.add_argument("--copy-kernel", type=int, default=0, metavar="BYTES",
                     help="only run one plain device-to-device copy of BYTES bytes (used to "
                          "calibrate the FETCH_SIZE / WRITE_SIZE counters) and exit")
@@ -211,6 +339,9 @@ def main():
 
     if args.batched_only:
         print(json.dumps({"batched_vs_loop": batched_leg(args.steps, args.warmup)}), flush=True)
+        return
+    if args.adjoint_only:
+        print(json.dumps({"adjoint_vs_plain": adjoint_leg(args.warmup)}), flush=True)
         return
 
     cfg = WORKLOADS[args.workload]
@@ -300,6 +431,8 @@ def main():
     }
     if not args.no_batched:
         out["batched_vs_loop"] = batched_leg(args.steps, args.warmup)
+    if not args.no_adjoint:
+        out["adjoint_vs_plain"] = adjoint_leg(args.warmup)
     if not args.no_cpu_baseline:
         log("timing the CPU oracle on a column sample")
         out["cpu_baseline"] = cpu_baseline(cfg, V, tau, Z, L_total)

@@ -125,6 +125,47 @@ int trbt_apply_z(int64_t n, int nbw, int64_t nev, const trbt_z *hh_v, const trbt
                  trbt_z *Z, int64_t ldz, void *work, size_t work_bytes, void *stream);
 
 /* ------------------------------------------------------------------------
+ * Adjoint (reverse-mode derivative) of the real back-transformation.
+ * With Z_out = H_0 H_1 ... H_{K-1} Z_in (Eq. 2stage_bkwd1, real reflectors
+ * H_k = I - tau_k v_k v_k^T) and G = dL/dZ_out for some scalar L, it returns
+ *   dL/dZ_in = H_{K-1}^T ... H_0^T G        (in place in G),
+ *   dL/dv    (K x nbw, row k = reflector k, zero beyond its length),
+ *   dL/dtau  (K).
+ * The intermediate states of the forward pass are recomputed from
+ * checkpoints taken every 16 stages (of the band's bulge-chasing stages,
+ * Sec. 2.2.1) by a first forward pass over a scratch copy of Z_in; the
+ * column sums that form dL/dv and dL/dtau are reduced in a fixed order, so
+ * results are bitwise reproducible.
+ * ------------------------------------------------------------------------ */
+
+/* Workspace bytes for the adjoint of (n, nbw, nev); ckpt_every is 0 or 16
+ * (the default, and the only interval implemented).  Errors: -1 n, -2 nbw,
+ * -3 nev, -4 ckpt_every, -5 null `bytes`.  The workspace is large: the
+ * checkpoints hold about n^2/(2 nbw) * (nbw + 16) * nev / 16 doubles and
+ * the per-strip column sums a similar amount. */
+int trbt_adjoint_workspace_bytes_d(int64_t n, int nbw, int64_t nev, int ckpt_every,
+                                   size_t *bytes);
+
+/* Arguments: 1 n >= 0, 2 nbw in [1, TRBT_NBW_MAX], 3 0 <= nev <= n,
+ * 4 hh_v, 5 hh_tau (device, as for the forward call), 6 Z_in (device,
+ * n x nev column-major, read only), 7 ldz >= max(1, n), 8 G (device,
+ * n x nev column-major: dL/dZ_out on entry, dL/dZ_in on exit),
+ * 9 ldg >= max(1, n), 10 dv (device, K x nbw, written entirely), 11 dtau
+ * (device, K), 12 ckpt_every (0 or 16), 13 work (device, aligned to
+ * TRBT_WORK_ALIGN), 14 work_bytes (at least trbt_adjoint_workspace_bytes_d),
+ * 15 stream.  Pointers may be NULL where nothing is read or written
+ * (K == 0, or nev == 0 for Z_in and G).  K == 0 returns without touching
+ * anything (dL/dZ_in = G); nev == 0 sets dv and dtau to zero.
+ * Asynchronous on `stream`; no allocation.  Returns TRBT_ERR_WORKSPACE when
+ * work is missing or too small. */
+int trans_ev_tridi_to_band_adjoint_d(int64_t n, int nbw, int64_t nev,
+                                     const double *hh_v, const double *hh_tau,
+                                     const double *Z_in, int64_t ldz,
+                                     double *G, int64_t ldg,
+                                     double *dv, double *dtau, int ckpt_every,
+                                     void *work, size_t work_bytes, void *stream);
+
+/* ------------------------------------------------------------------------
  * Batched back-transformation: many independent real problems of uneven
  * size (k-points, spin channels), each exactly the operation above, run
  * through one persistent launch per band width, captured once in a HIP graph.

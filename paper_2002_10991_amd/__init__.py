@@ -22,7 +22,8 @@ __all__ = [
     "trbt_apply_d", "trbt_apply_z", "trbt_strerror", "back_transform", "alloc_workspace",
     "TRBT_WORK_ALIGN", "TRBT_NBW_MAX", "trbt_problem_d", "trbt_plan_config",
     "trbt_plan_create_batched_d", "trbt_plan_exec", "trbt_plan_get_config", "trbt_plan_check",
-    "trbt_plan_destroy", "BatchedPlan",
+    "trbt_plan_destroy", "BatchedPlan", "trbt_adjoint_workspace_bytes_d",
+    "trans_ev_tridi_to_band_adjoint_d", "adjoint", "BackTransform", "back_transform_autograd",
 ]
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
@@ -67,6 +68,11 @@ def lib():
         for f in (L.trbt_prepare_d, L.trbt_prepare_z):
             f.argtypes = [i64, i32, vp, vp, vp, sz, vp]
             f.restype = i32
+        L.trbt_adjoint_workspace_bytes_d.argtypes = [i64, i32, i64, i32, C.POINTER(sz)]
+        L.trbt_adjoint_workspace_bytes_d.restype = i32
+        L.trans_ev_tridi_to_band_adjoint_d.argtypes = [i64, i32, i64, vp, vp, vp, i64, vp, i64,
+                                                       vp, vp, i32, vp, sz, vp]
+        L.trans_ev_tridi_to_band_adjoint_d.restype = i32
         L.trbt_plan_create_batched_d.argtypes = [C.POINTER(trbt_problem_d), i32,
                                                  C.POINTER(trbt_plan_config),
                                                  C.POINTER(vp), vp]
@@ -300,3 +306,112 @@ class BatchedPlan:
             self.close()
         except Exception:
             pass
+
+
+# --------------------------------------------------------------------------
+# Adjoint
+# --------------------------------------------------------------------------
+def trbt_adjoint_workspace_bytes_d(n: int, nbw: int, nev: int, ckpt_every: int = 16) -> int:
+    b = C.c_size_t()
+    rc = lib().trbt_adjoint_workspace_bytes_d(n, nbw, nev, ckpt_every, C.byref(b))
+    if rc:
+        raise TrbtError(rc, "trbt_adjoint_workspace_bytes_d")
+    return b.value
+
+
+def trans_ev_tridi_to_band_adjoint_d(n, nbw, nev, hh_v, hh_tau, Z_in, ldz, G, ldg, dv, dtau,
+                                     ckpt_every, work, work_bytes, stream=None) -> int:
+    """Status-returning call of the C entry point."""
+    return lib().trans_ev_tridi_to_band_adjoint_d(
+        n, nbw, nev, _ptr(hh_v), _ptr(hh_tau), _ptr(Z_in), ldz, _ptr(G), ldg, _ptr(dv),
+        _ptr(dtau), ckpt_every, _ptr(work), work_bytes, _stream(stream))
+
+
+def _colmajor(t):
+    """(n, nev) tensor -> (a new buffer (nev, n) contiguous holding a copy of
+    it, and the buffer's column-major (n, nev) view).  Always a copy: the
+    kernels work in place and must not write through an alias of t."""
+    import torch
+    buf = torch.empty((t.shape[1], t.shape[0]), dtype=t.dtype, device=t.device)
+    buf.copy_(t.t())
+    return buf, buf.t()
+
+
+def adjoint(Z_in, G, hh_v, hh_tau, nbw: int, work=None, stream=None):
+    """dL/dZ_in, dL/dv, dL/dtau of Z_out = H_0..H_{K-1} Z_in for G = dL/dZ_out.
+
+    Z_in, G: (n, nev) float64 tensors with unit row stride (column-major
+    views); G is overwritten with dL/dZ_in.  Returns (G, dv (K, nbw), dtau (K,))."""
+    import torch
+    n, nev = Z_in.shape
+    for name, t in (("Z_in", Z_in), ("G", G)):
+        if t.dtype != torch.float64:
+            raise TypeError(f"{name} must be float64")
+        if nev and n and t.stride(0) != 1:
+            raise ValueError(f"{name} must be column-major (unit row stride)")
+    K = trbt_num_reflectors(n, nbw)
+    dv = torch.empty(max(K, 1), nbw, dtype=torch.float64, device=G.device)[:K]
+    dt = torch.empty(max(K, 1), dtype=torch.float64, device=G.device)[:K]
+    if work is None:
+        nb = trbt_adjoint_workspace_bytes_d(n, nbw, nev)
+        if nb:
+            buf = torch.empty(nb + TRBT_WORK_ALIGN, dtype=torch.uint8, device=G.device)
+            work = buf[(-buf.data_ptr()) % TRBT_WORK_ALIGN:][:nb]
+    wb = 0 if work is None else work.numel() * work.element_size()
+    ldz = Z_in.stride(1) if nev > 1 else max(n, 1)
+    ldg = G.stride(1) if nev > 1 else max(n, 1)
+    rc = trans_ev_tridi_to_band_adjoint_d(n, nbw, nev, hh_v, hh_tau, Z_in, max(ldz, 1), G,
+                                          max(ldg, 1), dv if K else None, dt if K else None,
+                                          16, work, wb, stream)
+    if rc:
+        raise TrbtError(rc, "trans_ev_tridi_to_band_adjoint_d")
+    return G, dv, dt
+
+
+def _back_transform_function():
+    import torch
+
+    class BackTransform(torch.autograd.Function):
+        """Z_out = H_0 ... H_{K-1} Z_in (real) with the hand-written adjoint.
+
+        Saves only Z_in, hh_v and hh_tau; the backward pass recomputes the
+        forward states from checkpoints every 16 stages."""
+
+        @staticmethod
+        def forward(ctx, Z_in, hh_v, hh_tau, nbw):
+            zbuf, zin = _colmajor(Z_in.detach())
+            obuf, out = _colmajor(Z_in.detach())
+            v = hh_v.detach().contiguous()
+            t = hh_tau.detach().contiguous()
+            back_transform(out, v, t, nbw)
+            ctx.save_for_backward(zbuf, v, t)
+            ctx.nbw = nbw
+            return out
+
+        @staticmethod
+        def backward(ctx, grad_out):
+            zbuf, v, t = ctx.saved_tensors
+            gbuf, g = _colmajor(grad_out)
+            dz, dv, dt = adjoint(zbuf.t(), g, v, t, ctx.nbw)
+            return dz, dv, dt, None
+
+    return BackTransform
+
+
+class _Lazy:
+    fn = None
+
+
+def back_transform_autograd(Z_in, hh_v, hh_tau, nbw: int):
+    """Differentiable real back-transformation (torch.autograd)."""
+    if _Lazy.fn is None:
+        _Lazy.fn = _back_transform_function()
+    return _Lazy.fn.apply(Z_in, hh_v, hh_tau, nbw)
+
+
+def __getattr__(name):
+    if name == "BackTransform":
+        if _Lazy.fn is None:
+            _Lazy.fn = _back_transform_function()
+        return _Lazy.fn
+    raise AttributeError(name)

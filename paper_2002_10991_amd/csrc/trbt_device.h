@@ -203,22 +203,30 @@ struct Geo {
 //                                                  4NT + u*NT + (NT-1-q)
 // i.e. in exactly the order the main kernel consumes them.
 // --------------------------------------------------------------------------
-// pack_block packs block `blk` (slot-major numbering) of one problem into
-// ws (the problem's packed-block array); all 256 threads of the workgroup
-// take part.
+// Shared-memory image of one block's compact-WY factor (see above).
 template <int NB, bool CPLX>
-__device__ inline void pack_block(int64_t n, const double* __restrict__ hv,
-                                  const double* __restrict__ ht, double* __restrict__ ws,
-                                  int64_t blk)
-{
-    using G = Geo<NB, CPLX>;
-    constexpr int NT = G::NT, NC = G::NC, R = 16 * NT;
-    __shared__ double Vt[R][16][NC];
-    __shared__ double Gm[16][16][NC];
-    __shared__ double Tm[16][16][NC];
-    __shared__ double tau[16][NC];
-    __shared__ int64_t s_j, s_t;
+struct WyBlock {
+    static constexpr int NT = Geo<NB, CPLX>::NT, NC = Geo<NB, CPLX>::NC, R = 16 * NT;
+    double Vt[R][16][NC];
+    double Gm[16][16][NC];
+    double Tm[16][16][NC];
+    double tau[16][NC];
+    int64_t j, t;
+};
 
+// wy_factor fills W for block `blk` (slot-major numbering): the reflectors
+// in window layout, their Gram matrix and the forward factor T.  All 256
+// threads of the workgroup take part; W is complete on return.
+template <int NB, bool CPLX>
+__device__ inline void wy_factor(int64_t n, const double* __restrict__ hv,
+                                 const double* __restrict__ ht, int64_t blk,
+                                 WyBlock<NB, CPLX>& W)
+{
+    constexpr int NC = WyBlock<NB, CPLX>::NC, R = WyBlock<NB, CPLX>::R;
+    auto& Vt = W.Vt;
+    auto& Gm = W.Gm;
+    auto& Tm = W.Tm;
+    auto& tau = W.tau;
     const int tid = threadIdx.x;
     const int64_t nblk = (n - 2 + KB - 1) / KB;
     const int64_t J = sweeps_in_stage(n, NB, 0);
@@ -229,11 +237,11 @@ __device__ inline void pack_block(int64_t n, const double* __restrict__ hv,
             int64_t mid = (lo + hi) / 2;
             if (slot_base(mid, nblk, nt1) <= blk) lo = mid; else hi = mid;
         }
-        s_j = lo;
-        s_t = lo * nt1 + (blk - slot_base(lo, nblk, nt1));
+        W.j = lo;
+        W.t = lo * nt1 + (blk - slot_base(lo, nblk, nt1));
     }
     __syncthreads();
-    const int64_t j = s_j, t = s_t;
+    const int64_t j = W.j, t = W.t;
     const int64_t s_top = n - 3 - KB * t;
 
     for (int idx = tid; idx < R * 16; idx += 256) {
@@ -299,6 +307,23 @@ __device__ inline void pack_block(int64_t n, const double* __restrict__ hv,
         }
         __syncthreads();
     }
+}
+
+// pack_block packs block `blk` (slot-major numbering) of one problem into
+// ws (the problem's packed-block array); all 256 threads of the workgroup
+// take part.
+template <int NB, bool CPLX>
+__device__ inline void pack_block(int64_t n, const double* __restrict__ hv,
+                                  const double* __restrict__ ht, double* __restrict__ ws,
+                                  int64_t blk)
+{
+    using G = Geo<NB, CPLX>;
+    constexpr int NT = G::NT, NC = G::NC;
+    __shared__ WyBlock<NB, CPLX> W;
+    wy_factor<NB, CPLX>(n, hv, ht, blk, W);
+    const auto& Vt = W.Vt;
+    const auto& Tm = W.Tm;
+    const int tid = threadIdx.x;
     // A1 chunks and -V chunks
     double* out = ws + (size_t)blk * G::PB;
     for (int idx = tid; idx < NT * 4 * 64; idx += 256) {
@@ -476,11 +501,18 @@ __device__ inline void load_chunk(const double* __restrict__ blkp, int c, int la
 // is the problem's packed-block array, prog the workgroup's LDS progress
 // array, all zero on entry.  On the (never expected) time-out of a progress
 // wait a wave sets *err and leaves.
-template <int NB, int CT, bool CPLX, int D, int NW>
+//
+// With CKPT (the first pass of the adjoint), every block's input window is
+// also written to ckpt, one 16x16 tile at a time in register order:
+//   ckpt[(((b * NT + q) * nstrips + strip) * 4 + e) * 64 + lane]
+// b = the block's slot-major index, q = tile of the window, e = element.
+template <int NB, int CT, bool CPLX, int D, int NW, bool CKPT = false>
 __device__ inline void blocked_strip(int64_t n, int64_t nev, const double* __restrict__ wsb,
                                      double* __restrict__ Z, int64_t ldz,
-                                     unsigned* __restrict__ err, int64_t strip, int* prog)
+                                     unsigned* __restrict__ err, int64_t strip, int* prog,
+                                     double* __restrict__ ckpt = nullptr, int64_t nstrips = 0)
 {
+    static_assert(!CKPT || (CT == 1 && !CPLX), "checkpoints: real, one 16-column tile");
     using G = Geo<NB, CPLX>;
     constexpr int NT = G::NT;
     constexpr int NCH = 8 * NT;            // operand chunks per block
@@ -519,6 +551,15 @@ __device__ inline void blocked_strip(int64_t n, int64_t nev, const double* __res
 
         for (int64_t t = t0; t < nblk; ++t, blkp += G::PB, p0 -= KB) {
             const bool has_next = t + 1 < nblk;
+            if constexpr (CKPT) {
+                double* cp = ckpt + ((size_t)(slot_base(j, nblk, nt1) + t - t0) * NT * nstrips +
+                                     strip) * 256 + lane;
+#pragma unroll
+                for (int q = 0; q < NT; ++q)
+#pragma unroll
+                    for (int e = 0; e < 4; ++e)
+                        cp[(size_t)q * nstrips * 256 + e * 64] = zt[q][0].re[e];
+            }
             // the top tile of the next block: slot j-1 must have retired it
             Tile<CPLX> znext[CT];
             if (has_next) {

@@ -142,3 +142,40 @@ def test_plan_validation_codes(T):
     assert lib.trbt_plan_exec(None, None) == -1
     assert lib.trbt_plan_get_config(None, None, None) == -1
     assert lib.trbt_plan_destroy(None) == 0
+
+
+def test_adjoint_validation_codes(T):
+    """The adjoint entry point checks its 15 arguments on the host, in order,
+    before any HIP call."""
+    f = T.trans_ev_tridi_to_band_adjoint_d
+    ok = dict(n=100, nbw=32, nev=10, hh_v=FAKE, hh_tau=FAKE, Z_in=FAKE, ldz=100, G=FAKE, ldg=100,
+              dv=FAKE, dtau=FAKE, ckpt=16, work=None, wb=0)
+
+    def call(**kw):
+        a = dict(ok, **kw)
+        return f(a["n"], a["nbw"], a["nev"], a["hh_v"], a["hh_tau"], a["Z_in"], a["ldz"], a["G"],
+                 a["ldg"], a["dv"], a["dtau"], a["ckpt"], a["work"], a["wb"], 0)
+
+    assert call(n=-1) == -1
+    assert call(nbw=0) == -2
+    assert call(nev=101) == -3
+    assert call(hh_v=None) == -4
+    assert call(hh_tau=None) == -5
+    assert call(Z_in=None) == -6
+    assert call(ldz=99) == -7
+    assert call(G=None) == -8
+    assert call(ldg=50) == -9
+    assert call(dv=None) == -10
+    assert call(dtau=None) == -11
+    assert call(ckpt=8) == -12
+    assert call(work=FAKE + 8) == -13
+    assert call(work=None, wb=64) == -13
+    assert call(nbw=1, hh_v=None, hh_tau=None, dv=None, dtau=None) == 0   # K == 0: no-op
+    assert T.trbt_adjoint_workspace_bytes_d(100, 32, 10, 16) > 0
+    assert T.trbt_adjoint_workspace_bytes_d(100, 32, 0, 16) == 0
+    assert T.trbt_adjoint_workspace_bytes_d(100, 1, 10, 16) == 0
+    for bad, code in [((-1, 32, 10, 16), -1), ((100, 0, 10, 16), -2), ((100, 32, 200, 16), -3),
+                      ((100, 32, 10, 5), -4)]:
+        with pytest.raises(T.TrbtError) as e:
+            T.trbt_adjoint_workspace_bytes_d(*bad)
+        assert e.value.status == code
