@@ -27,7 +27,7 @@ int prepare(int64_t n, int nbw, const double* hv, const double* ht, void* work,
     if (K > 0 && !ht) return -4;
     if (work && ((uintptr_t)work % TRBT_WORK_ALIGN)) return -5;
     if (work_bytes && !work) return -5;
-    if (K == 0 || !blocked_eligible(nbw)) return TRBT_SUCCESS;
+    if (K == 0 || !use_blocked(n, nbw, CPLX)) return TRBT_SUCCESS;
     if (!work || work_bytes < blocked_bytes(n, nbw, CPLX)) return TRBT_ERR_WORKSPACE;
     int rc = check_device();
     if (rc) return rc;
@@ -62,7 +62,7 @@ int apply(int64_t n, int nbw, int64_t nev, const double* hv, const double* ht, d
     if (rc) return rc;
     hipStream_t st = (hipStream_t)stream_v;
 
-    if (blocked_eligible(nbw)) {
+    if (use_blocked(n, nbw, CPLX)) {
         if (work_bytes < blocked_bytes(n, nbw, CPLX) || !work) return TRBT_ERR_WORKSPACE;
         const double* ws = (const double*)work;
         const int CT = 1;
@@ -134,7 +134,7 @@ int trbt_workspace_bytes(int64_t n, int nbw, int64_t nev, int is_complex, size_t
     if (nbw < 1 || nbw > TRBT_NBW_MAX) return -2;
     if (nev < 0 || nev > n) return -3;
     if (!bytes) return -4;
-    *bytes = (blocked_eligible(nbw) && num_reflectors(n, nbw) > 0 && nev > 0)
+    *bytes = (use_blocked(n, nbw, is_complex != 0) && num_reflectors(n, nbw) > 0 && nev > 0)
                  ? blocked_bytes(n, nbw, is_complex != 0)
                  : 0;
     return TRBT_SUCCESS;

@@ -602,7 +602,7 @@ AdjLayout adj_layout(int64_t n, int nbw, int64_t nev)
     size_t off = HDR_BYTES;
     L.zs = off;
     off = al(off + (size_t)n * nev * sizeof(double));
-    if (blocked_eligible(nbw)) {
+    if (use_blocked(n, nbw, false)) {
         const int nt = adj_tiles(nbw);
         L.nblocks = blocked_num_blocks(n, nbw);
         L.nstrips = (nev + 15) / 16;
@@ -728,7 +728,7 @@ int trans_ev_tridi_to_band_adjoint_d(int64_t n, int nbw, int64_t nev, const doub
                          (size_t)n * sizeof(double), (size_t)nev, hipMemcpyDeviceToDevice,
                          st) != hipSuccess)
         return TRBT_ERR_HIP;
-    if (blocked_eligible(nbw)) {
+    if (use_blocked(n, nbw, false)) {
         switch (nbw) {
             case 16: launch_blocked_adjoint<16>(n, nev, hh_v, hh_tau, G, ldg, dv, dtau, ws, L, st); break;
             case 32: launch_blocked_adjoint<32>(n, nev, hh_v, hh_tau, G, ldg, dv, dtau, ws, L, st); break;

@@ -179,7 +179,7 @@ namespace {
 
 int64_t problem_cost(const trbt_problem_d& p)
 {   // MFMA work of one strip ~ number of packed blocks; streaming ~ L
-    return blocked_eligible(p.nbw) ? blocked_num_blocks(p.n, p.nbw)
+    return use_blocked(p.n, p.nbw, false) ? blocked_num_blocks(p.n, p.nbw)
                                    : num_reflectors(p.n, p.nbw) * p.nbw / 16;
 }
 
@@ -261,7 +261,7 @@ int build_tables(trbt_plan& P, const std::vector<double*>& zptr)
         for (int i = 0; i < count; ++i) {
             const trbt_problem_d& p = P.probs[i];
             if (num_reflectors(p.n, p.nbw) == 0 || p.nev == 0) continue;
-            const bool elig = blocked_eligible(p.nbw) && !stream_all;
+            const bool elig = use_blocked(p.n, p.nbw, false) && !stream_all;
             if (g.blocked ? (elig && p.nbw == g.nbw) : (gi == 4 && !elig)) g.members.push_back(i);
         }
         if (!g.members.empty()) P.groups.push_back(g);
@@ -458,7 +458,7 @@ int tune(trbt_plan& P)
     }
     bool any_blocked = false;
     for (const trbt_problem_d& p : P.probs)
-        any_blocked |= blocked_eligible(p.nbw) && num_reflectors(p.n, p.nbw) > 0 && p.nev > 0;
+        any_blocked |= use_blocked(p.n, p.nbw, false) && num_reflectors(p.n, p.nbw) > 0 && p.nev > 0;
     std::vector<trbt_plan_config> cands;
     if (any_blocked) {
         for (int cols : {16, 32})
@@ -524,7 +524,7 @@ int trbt_plan_create_batched_d(const trbt_problem_d* probs, int count,
     for (int i = 0; i < count; ++i) {
         const trbt_problem_d& p = probs[i];
         const bool active = num_reflectors(p.n, p.nbw) > 0 && p.nev > 0;
-        if (active && blocked_eligible(p.nbw)) {
+        if (active && use_blocked(p.n, p.nbw, false)) {
             off = align_up(off, 256);
             P->ws_off[i] = off;
             off += blocked_bytes(p.n, p.nbw, false) - HDR_BYTES;

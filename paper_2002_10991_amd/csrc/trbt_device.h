@@ -344,10 +344,12 @@ __device__ inline void pack_block(int64_t n, const double* __restrict__ hv,
             out[qu * G::CHUNK + lane] = ar;
             if (CPLX) out[qu * G::CHUNK + 64 + lane] = ai;
         }
-        {   // -V chunks in the order the main kernel reads them: u ascending,
-            // and within each u the tiles from the bottom of the window up
+        {   // -V chunks in the order the main kernel reads them.  Real: u
+            // ascending, and within each u the tiles from the bottom of the
+            // window up.  Complex: tile by tile from the bottom up, u
+            // ascending inside a tile.
             const int r = 16 * q + lane % 16, p = 4 * u + lane / 16;
-            const int pos = u * NT + (NT - 1 - q);
+            const int pos = CPLX ? (NT - 1 - q) * 4 + u : u * NT + (NT - 1 - q);
             out[G::A1_DBL + pos * G::CHUNK + lane] = -Vt[r][p][0];
             if (CPLX) out[G::A1_DBL + pos * G::CHUNK + 64 + lane] = -Vt[r][p][NC - 1];
         }
@@ -478,14 +480,29 @@ __host__ __device__ constexpr int ring_depth()
     return CPLX ? 8 : 4 * Geo<NB, CPLX>::NT;
 }
 
+// Operand chunks are read through a buffer resource holding the slot's
+// operand stream (all of its blocks, contiguous): the per-lane offset is a
+// constant register and the chunk offset a scalar, so the loads need no
+// vector address arithmetic.
+__device__ inline __amdgpu_buffer_rsrc_t stream_rsrc(const double* base, uint32_t bytes)
+{
+    return __builtin_amdgcn_make_buffer_rsrc(const_cast<double*>(base), 0, (int)bytes,
+                                             0x00020000);
+}
+
+__device__ inline double buffer_load_f64(__amdgpu_buffer_rsrc_t r, uint32_t voff, uint32_t soff)
+{
+    return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(r, voff, soff, 0));
+}
+
 template <bool CPLX, int D>
-__device__ inline void load_chunk(const double* __restrict__ blkp, int c, int lane,
+__device__ inline void load_chunk(__amdgpu_buffer_rsrc_t r, uint32_t boff, int c, int lane,
                                   double (&re)[D], double (&im)[D], int slot)
 {
-    constexpr int CH = CPLX ? 128 : 64;
-    const double* p = blkp + c * CH;
-    re[slot] = p[lane];
-    if constexpr (CPLX) im[slot] = p[64 + lane];
+    constexpr uint32_t CH = CPLX ? 128 : 64;
+    const uint32_t soff = boff + (uint32_t)c * CH * 8;
+    re[slot] = buffer_load_f64(r, lane * 8, soff);
+    if constexpr (CPLX) im[slot] = buffer_load_f64(r, lane * 8 + 512, soff);
 }
 
 // Main blocked kernel.  Per block the operand stream is consumed in order:
@@ -534,7 +551,11 @@ __device__ inline void blocked_strip(int64_t n, int64_t nev, const double* __res
 
     for (int64_t j = w; j < J; j += NW) {
         const int64_t t0 = j * nt1;
-        const double* __restrict__ blkp = wsb + (size_t)slot_base(j, nblk, nt1) * G::PB;
+        // the slot's operand stream; blocks are PB doubles apart
+        const __amdgpu_buffer_rsrc_t ops =
+            stream_rsrc(wsb + (size_t)slot_base(j, nblk, nt1) * G::PB,
+                        (uint32_t)((nblk - t0) * G::PB * sizeof(double)));
+        uint32_t boff = 0;
         const int need0 = (int)((j - 1) * (nblk + 1));   // + t + 1: slot j-1 done block t
         if (j > 0 && !wait_progress(prog, wprev, need0 + (int)t0 + 1, err, lane)) return;
         int64_t p0 = n - 3 - KB * t0 - 15 + j * NB;
@@ -547,9 +568,9 @@ __device__ inline void blocked_strip(int64_t n, int64_t nev, const double* __res
                                 col_base + 16 * c, inside);
         }
 #pragma unroll
-        for (int c = 0; c < D; ++c) load_chunk<CPLX, D>(blkp, c, lane, ring_re, ring_im, c);
+        for (int c = 0; c < D; ++c) load_chunk<CPLX, D>(ops, 0, c, lane, ring_re, ring_im, c);
 
-        for (int64_t t = t0; t < nblk; ++t, blkp += G::PB, p0 -= KB) {
+        for (int64_t t = t0; t < nblk; ++t, boff += G::PB * sizeof(double), p0 -= KB) {
             const bool has_next = t + 1 < nblk;
             if constexpr (CKPT) {
                 double* cp = ckpt + ((size_t)(slot_base(j, nblk, nt1) + t - t0) * NT * nstrips +
@@ -571,71 +592,124 @@ __device__ inline void blocked_strip(int64_t n, int64_t nev, const double* __res
                                     inside);
             }
 
-            Tile<CPLX> y[2][CT];   // two partial sums: more independent MFMA chains
-#pragma unroll
-            for (int h = 0; h < 2; ++h)
-#pragma unroll
-                for (int c = 0; c < CT; ++c) {
-                    y[h][c].re = d4{0.0, 0.0, 0.0, 0.0};
-                    if constexpr (CPLX) y[h][c].im = d4{0.0, 0.0, 0.0, 0.0};
-                }
             Tile<CPLX> zsh[NT + 1][CT];   // window after the slide; zsh[NT] retires
-
-#pragma unroll
-            for (int c = 0; c < NCH; ++c) {
+            // operand chunk c of this block: read from the ring, then refill
+            // the ring slot with chunk c + D (running into the next block)
+            auto next_chunk = [&](int c, double& ar, double& ai) {
                 const int slot = c % D;
-                const double ar = ring_re[slot];
-                const double ai = CPLX ? ring_im[slot] : 0.0;
+                ar = ring_re[slot];
+                ai = CPLX ? ring_im[slot] : 0.0;
                 if (c + D < NCH)
-                    load_chunk<CPLX, D>(blkp, c + D, lane, ring_re, ring_im, slot);
+                    load_chunk<CPLX, D>(ops, boff, c + D, lane, ring_re, ring_im, slot);
                 else if (has_next)
-                    load_chunk<CPLX, D>(blkp + G::PB, c + D - NCH, lane, ring_re, ring_im, slot);
-                if (c < 4 * NT) {
-                    // Y += A1(:, chunk) * Zwin(chunk, :)
-                    const int q = c / 4, u = c % 4, h = q & 1;
+                    load_chunk<CPLX, D>(ops, boff + G::PB * sizeof(double), c + D - NCH, lane,
+                                        ring_re, ring_im, slot);
+            };
+            auto store_bottom = [&]() {   // the retiring tile, once it is final
+                if (has_next) {
+#pragma unroll
+                    for (int cc = 0; cc < CT; ++cc)
+                        store_tile<CPLX>(zsh[NT][cc], Z, ldz, n, nev, p0 + 16 * (NT - 1) + rsub,
+                                         col_base + 16 * cc);
+                }
+            };
+
+            if constexpr (CPLX) {
+                // Complex products with three real MFMAs each (Gauss):
+                //   (a + ib)(x + iy) = (ax - by) + i((a + b)(x + y) - ax - by)
+                // GEMM1: Y = A1 * Zwin, accumulating ax, by and (a+b)(x+y).
+                d4 ya[CT], yb[CT], yc[CT];
+#pragma unroll
+                for (int cc = 0; cc < CT; ++cc) ya[cc] = yb[cc] = yc[cc] = d4{0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+                for (int c = 0; c < 4 * NT; ++c) {
+                    double ar, ai;
+                    next_chunk(c, ar, ai);
+                    const double as = ar + ai;
+                    const int q = c / 4, u = c % 4;
 #pragma unroll
                     for (int cc = 0; cc < CT; ++cc) {
-                        if constexpr (CPLX) {
-                            y[h][cc].re = mfma_n<0>(ar, zt[q][cc].re[u], y[h][cc].re);
-                            y[h][cc].im = mfma_n<0>(ar, zt[q][cc].im[u], y[h][cc].im);
-                            y[h][cc].re = mfma_n<1>(ai, zt[q][cc].im[u], y[h][cc].re);
-                            y[h][cc].im = mfma_n<0>(ai, zt[q][cc].re[u], y[h][cc].im);
+                        const double zr = zt[q][cc].re[u], zi = zt[q][cc].im[u];
+                        ya[cc] = mfma_n<0>(ar, zr, ya[cc]);
+                        yb[cc] = mfma_n<0>(ai, zi, yb[cc]);
+                        yc[cc] = mfma_n<0>(as, zr + zi, yc[cc]);
+                    }
+                }
+                Tile<true> y[CT];
+                double ys[CT][4];
+#pragma unroll
+                for (int cc = 0; cc < CT; ++cc) {
+                    y[cc].re = ya[cc] - yb[cc];
+                    y[cc].im = yc[cc] - ya[cc] - yb[cc];
+#pragma unroll
+                    for (int u = 0; u < 4; ++u) ys[cc][u] = y[cc].re[u] + y[cc].im[u];
+                }
+                // GEMM2: Zwin += (-V) * Y, tile by tile from the bottom of the
+                // window up (the retiring tile first); the result of tile q
+                // lands in zsh[q+1], which slides the window by one tile.
+#pragma unroll
+                for (int c2 = 0; c2 < 4 * NT; ++c2) {
+                    double ar, ai;
+                    next_chunk(4 * NT + c2, ar, ai);
+                    const double as = ar + ai;
+                    const int q = NT - 1 - c2 / 4, u = c2 % 4;
+#pragma unroll
+                    for (int cc = 0; cc < CT; ++cc) {
+                        // per tile: sum of ax in zsh.re, sum of by in zt.im (free
+                        // after its use as a B operand in GEMM1), and
+                        // Z.im + sum of (a+b)(x+y) directly in zsh.im
+                        if (u == 0) {
+                            zsh[q + 1][cc].re = mfma_n<0>(ar, y[cc].re[0], d4{0.0, 0.0, 0.0, 0.0});
+                            zsh[q + 1][cc].im = mfma_n<0>(as, ys[cc][0], zt[q][cc].im);
+                            zt[q][cc].im = mfma_n<0>(ai, y[cc].im[0], d4{0.0, 0.0, 0.0, 0.0});
                         } else {
-                            y[h][cc].re = mfma_n<0>(ar, zt[q][cc].re[u], y[h][cc].re);
+                            zsh[q + 1][cc].re = mfma_n<0>(ar, y[cc].re[u], zsh[q + 1][cc].re);
+                            zsh[q + 1][cc].im = mfma_n<0>(as, ys[cc][u], zsh[q + 1][cc].im);
+                            zt[q][cc].im = mfma_n<0>(ai, y[cc].im[u], zt[q][cc].im);
+                        }
+                        if (u == 3) {
+                            const d4 ta = zsh[q + 1][cc].re, tb = zt[q][cc].im;
+                            zsh[q + 1][cc].re = zt[q][cc].re + (ta - tb);
+                            zsh[q + 1][cc].im = zsh[q + 1][cc].im - (ta + tb);
                         }
                     }
-                    if (c == 4 * NT - 1) {
+                    if (u == 3 && q == NT - 1) store_bottom();
+                }
+            } else {
+                Tile<CPLX> y[2][CT];   // two partial sums: more independent MFMA chains
+#pragma unroll
+                for (int h = 0; h < 2; ++h)
+#pragma unroll
+                    for (int c = 0; c < CT; ++c) y[h][c].re = d4{0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+                for (int c = 0; c < NCH; ++c) {
+                    double ar, ai;
+                    next_chunk(c, ar, ai);
+                    if (c < 4 * NT) {
+                        // Y += A1(:, chunk) * Zwin(chunk, :)
+                        const int q = c / 4, u = c % 4, h = q & 1;
+#pragma unroll
+                        for (int cc = 0; cc < CT; ++cc)
+                            y[h][cc].re = mfma_n<0>(ar, zt[q][cc].re[u], y[h][cc].re);
+                        if (c == 4 * NT - 1) {
+#pragma unroll
+                            for (int cc = 0; cc < CT; ++cc) y[0][cc].re += y[1][cc].re;
+                        }
+                    } else {
+                        // Zwin(tile q, :) += (-V)(tile q, chunk u) * Y(chunk u, :)
+                        const int c2 = c - 4 * NT, u = c2 / NT, q = NT - 1 - c2 % NT;
 #pragma unroll
                         for (int cc = 0; cc < CT; ++cc) {
-                            y[0][cc].re += y[1][cc].re;
-                            if constexpr (CPLX) y[0][cc].im += y[1][cc].im;
-                        }
-                    }
-                } else {
-                    // Zwin(tile q, :) += (-V)(tile q, chunk u) * Y(chunk u, :)
-                    const int c2 = c - 4 * NT, u = c2 / NT, q = NT - 1 - c2 % NT;
-#pragma unroll
-                    for (int cc = 0; cc < CT; ++cc) {
-                        const Tile<CPLX>& src = zt[q][cc];
-                        Tile<CPLX>& dst = (u == 3) ? zsh[q + 1][cc] : zt[q][cc];
-                        if constexpr (CPLX) {
-                            const d4 re = mfma_n<0>(ar, y[0][cc].re[u], src.re);
-                            const d4 im = mfma_n<0>(ar, y[0][cc].im[u], src.im);
-                            dst.re = mfma_n<2>(ai, y[0][cc].im[u], re);
-                            dst.im = mfma_n<0>(ai, y[0][cc].re[u], im);
-                        } else {
+                            const Tile<CPLX>& src = zt[q][cc];
+                            Tile<CPLX>& dst = (u == 3) ? zsh[q + 1][cc] : zt[q][cc];
                             dst.re = mfma_n<0>(ar, y[0][cc].re[u], src.re);
                         }
+                        if (u == 3 && q == NT - 1) store_bottom();
                     }
                 }
             }
 
-            if (has_next) {
-#pragma unroll
-                for (int c = 0; c < CT; ++c)
-                    store_tile<CPLX>(zsh[NT][c], Z, ldz, n, nev, p0 + 16 * (NT - 1) + rsub,
-                                     col_base + 16 * c);
-            } else {
+            if (!has_next) {
 #pragma unroll
                 for (int q = 0; q < NT; ++q)
 #pragma unroll
@@ -694,6 +768,22 @@ inline int check_device()
 }
 
 inline bool blocked_eligible(int nbw) { return nbw == 16 || nbw == 32 || nbw == 48 || nbw == 64; }
+
+// The blocked kernels address one slot's operand stream (at most
+// ceil((n-2)/16) blocks) through a 32-bit buffer range.
+inline bool blocked_fits(int64_t n, int nbw, bool cplx)
+{
+    const int64_t nblk = (n - 2 + KB - 1) / KB;
+    const int64_t pb = (int64_t)2 * (nbw / 16 + 1) * 4 * 64 * (cplx ? 2 : 1);
+    return nblk * pb * (int64_t)sizeof(double) < ((int64_t)1 << 31);
+}
+
+// Problems the blocked (compact-WY, MFMA) kernels take; the rest run the
+// unblocked ones.
+inline bool use_blocked(int64_t n, int nbw, bool cplx)
+{
+    return blocked_eligible(nbw) && blocked_fits(n, nbw, cplx);
+}
 
 inline size_t blocked_bytes(int64_t n, int nbw, bool cplx)
 {
