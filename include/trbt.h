@@ -215,7 +215,9 @@ typedef struct trbt_plan trbt_plan;   /* opaque */
  * life) and captures the launch sequence into a graph.  With cfg == NULL it
  * first times every candidate configuration on device scratch copies of the
  * problems' Z (freed before returning) and keeps the fastest; the caller's
- * Z is not modified. */
+ * Z is not modified.  Candidates: strip_cols 16/32 x waves 4/8 with
+ * block_stages 16, and block_stages 1 when no problem can take the blocked
+ * form or every problem has n <= 256. */
 int trbt_plan_create_batched_d(const trbt_problem_d *probs, int count,
                                const trbt_plan_config *cfg, trbt_plan **plan,
                                void *stream);

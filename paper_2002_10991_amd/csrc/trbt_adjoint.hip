@@ -265,7 +265,8 @@ __global__ __launch_bounds__(64 * NW) void k_adj_blocked(int64_t n, int64_t nev,
             // slide down: the top tile leaves for slot j-1, a new bottom tile
             // arrives from slot j+1 (or from G when slot j+1 has no block)
             if (t > t0) {
-                store_tile<false>(g[0], G, ldg, n, nev, p0 + rsub, col);
+                store_tile<false>(g[0], G, ldg, n, nev, p0 + rsub, col,
+                                  cols_inside && p0 >= 0 && p0 + 16 <= n);
                 __hip_atomic_store(&prog[w], base + (int)(nblk - t), __ATOMIC_RELEASE,
                                    __HIP_MEMORY_SCOPE_WORKGROUP);
 #pragma unroll

@@ -29,7 +29,8 @@
 //
 // Tuning: without a fixed configuration, plan creation times every
 // candidate (strip width 16 or 32 columns, 4 or 8 waves per workgroup,
-// 16-stage compact-WY blocks or one reflector at a time) on scratch copies
+// 16-stage compact-WY blocks; one reflector at a time as well when no
+// problem can take the blocked form or all have n <= 256) on scratch copies
 // of the problems' Z and keeps the fastest.
 
 #include <hip/hip_runtime.h>
@@ -457,14 +458,21 @@ int tune(trbt_plan& P)
         }
     }
     bool any_blocked = false;
-    for (const trbt_problem_d& p : P.probs)
-        any_blocked |= use_blocked(p.n, p.nbw, false) && num_reflectors(p.n, p.nbw) > 0 && p.nev > 0;
+    int64_t max_n = 0;
+    for (const trbt_problem_d& p : P.probs) {
+        const bool active = num_reflectors(p.n, p.nbw) > 0 && p.nev > 0;
+        any_blocked |= active && use_blocked(p.n, p.nbw, false);
+        if (active) max_n = std::max(max_n, p.n);
+    }
     std::vector<trbt_plan_config> cands;
     if (any_blocked) {
         for (int cols : {16, 32})
             for (int waves : {8, 4}) cands.push_back({cols, waves, 16});
     }
-    cands.push_back({16, 8, 1});
+    // The streaming form (one lane per column, a dependent chain of K
+    // reflectors per lane) only competes on tiny problems; beyond that a
+    // single timing of it costs more than the whole plan's other candidates.
+    if (!any_blocked || max_n <= 256) cands.push_back({16, 8, 1});
     trbt_plan_config best{16, 8, 16};
     double best_ms = 1e300;
     for (const trbt_plan_config& c : cands) {

@@ -438,10 +438,25 @@ __device__ inline void load_tile(Tile<CPLX>& t, const double* __restrict__ Z, in
     }
 }
 
+// Tile store; `interior` (wave-uniform: all 16 rows inside the matrix and
+// the whole strip inside nev) skips the per-row checks.
 template <bool CPLX>
 __device__ inline void store_tile(const Tile<CPLX>& t, double* __restrict__ Z, int64_t ldz,
-                                  int64_t n, int64_t nev, int64_t row0, int64_t col)
+                                  int64_t n, int64_t nev, int64_t row0, int64_t col,
+                                  bool interior = false)
 {
+    if (interior) {
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+            const int64_t r = row0 + 4 * e;
+            if constexpr (CPLX) {
+                *(d2*)(Z + 2 * (col * ldz + r)) = d2{t.re[e], t.im[e]};
+            } else {
+                Z[col * ldz + r] = t.re[e];
+            }
+        }
+        return;
+    }
     if (col >= nev) return;
 #pragma unroll
     for (int e = 0; e < 4; ++e) {
@@ -593,12 +608,13 @@ __device__ inline void blocked_strip(int64_t n, int64_t nev, const double* __res
             }
 
             Tile<CPLX> zsh[NT + 1][CT];   // window after the slide; zsh[NT] retires
-            // operand chunk c of this block: read from the ring, then refill
-            // the ring slot with chunk c + D (running into the next block)
-            auto next_chunk = [&](int c, double& ar, double& ai) {
+            // operand chunk c of this block sits in ring slot c % D; as soon
+            // as it has been read the slot is refilled with chunk c + D
+            // (running into the next block).  (Refilling only after the
+            // chunk's MFMAs saves register copies but makes the load wait for
+            // the MFMA to read its operand: slower.)
+            auto refill = [&](int c) {
                 const int slot = c % D;
-                ar = ring_re[slot];
-                ai = CPLX ? ring_im[slot] : 0.0;
                 if (c + D < NCH)
                     load_chunk<CPLX, D>(ops, boff, c + D, lane, ring_re, ring_im, slot);
                 else if (has_next)
@@ -607,10 +623,12 @@ __device__ inline void blocked_strip(int64_t n, int64_t nev, const double* __res
             };
             auto store_bottom = [&]() {   // the retiring tile, once it is final
                 if (has_next) {
+                    const int64_t rb = p0 + 16 * (NT - 1);
+                    const bool inside = cols_inside && rb >= 0 && rb + 16 <= n;
 #pragma unroll
                     for (int cc = 0; cc < CT; ++cc)
-                        store_tile<CPLX>(zsh[NT][cc], Z, ldz, n, nev, p0 + 16 * (NT - 1) + rsub,
-                                         col_base + 16 * cc);
+                        store_tile<CPLX>(zsh[NT][cc], Z, ldz, n, nev, rb + rsub,
+                                         col_base + 16 * cc, inside);
                 }
             };
 
@@ -623,8 +641,8 @@ __device__ inline void blocked_strip(int64_t n, int64_t nev, const double* __res
                 for (int cc = 0; cc < CT; ++cc) ya[cc] = yb[cc] = yc[cc] = d4{0.0, 0.0, 0.0, 0.0};
 #pragma unroll
                 for (int c = 0; c < 4 * NT; ++c) {
-                    double ar, ai;
-                    next_chunk(c, ar, ai);
+                    const double ar = ring_re[c % D], ai = ring_im[c % D];
+                    refill(c);
                     const double as = ar + ai;
                     const int q = c / 4, u = c % 4;
 #pragma unroll
@@ -649,28 +667,30 @@ __device__ inline void blocked_strip(int64_t n, int64_t nev, const double* __res
                 // lands in zsh[q+1], which slides the window by one tile.
 #pragma unroll
                 for (int c2 = 0; c2 < 4 * NT; ++c2) {
-                    double ar, ai;
-                    next_chunk(4 * NT + c2, ar, ai);
+                    const int c = 4 * NT + c2;
+                    const double ar = ring_re[c % D], ai = ring_im[c % D];
+                    refill(c);
                     const double as = ar + ai;
                     const int q = NT - 1 - c2 / 4, u = c2 % 4;
 #pragma unroll
                     for (int cc = 0; cc < CT; ++cc) {
-                        // per tile: sum of ax in zsh.re, sum of by in zt.im (free
+                        // per tile: sum of ax in dst.re, sum of by in zt.im (free
                         // after its use as a B operand in GEMM1), and
-                        // Z.im + sum of (a+b)(x+y) directly in zsh.im
+                        // Z.im + sum of (a+b)(x+y) directly in dst.im
+                        Tile<true>& dst = zsh[q + 1][cc];
                         if (u == 0) {
-                            zsh[q + 1][cc].re = mfma_n<0>(ar, y[cc].re[0], d4{0.0, 0.0, 0.0, 0.0});
-                            zsh[q + 1][cc].im = mfma_n<0>(as, ys[cc][0], zt[q][cc].im);
+                            dst.re = mfma_n<0>(ar, y[cc].re[0], d4{0.0, 0.0, 0.0, 0.0});
+                            dst.im = mfma_n<0>(as, ys[cc][0], zt[q][cc].im);
                             zt[q][cc].im = mfma_n<0>(ai, y[cc].im[0], d4{0.0, 0.0, 0.0, 0.0});
                         } else {
-                            zsh[q + 1][cc].re = mfma_n<0>(ar, y[cc].re[u], zsh[q + 1][cc].re);
-                            zsh[q + 1][cc].im = mfma_n<0>(as, ys[cc][u], zsh[q + 1][cc].im);
+                            dst.re = mfma_n<0>(ar, y[cc].re[u], dst.re);
+                            dst.im = mfma_n<0>(as, ys[cc][u], dst.im);
                             zt[q][cc].im = mfma_n<0>(ai, y[cc].im[u], zt[q][cc].im);
                         }
                         if (u == 3) {
-                            const d4 ta = zsh[q + 1][cc].re, tb = zt[q][cc].im;
-                            zsh[q + 1][cc].re = zt[q][cc].re + (ta - tb);
-                            zsh[q + 1][cc].im = zsh[q + 1][cc].im - (ta + tb);
+                            const d4 ta = dst.re, tb = zt[q][cc].im;
+                            dst.re = zt[q][cc].re + (ta - tb);
+                            dst.im = dst.im - (ta + tb);
                         }
                     }
                     if (u == 3 && q == NT - 1) store_bottom();
@@ -683,8 +703,8 @@ __device__ inline void blocked_strip(int64_t n, int64_t nev, const double* __res
                     for (int c = 0; c < CT; ++c) y[h][c].re = d4{0.0, 0.0, 0.0, 0.0};
 #pragma unroll
                 for (int c = 0; c < NCH; ++c) {
-                    double ar, ai;
-                    next_chunk(c, ar, ai);
+                    const double ar = ring_re[c % D];
+                    refill(c);
                     if (c < 4 * NT) {
                         // Y += A1(:, chunk) * Zwin(chunk, :)
                         const int q = c / 4, u = c % 4, h = q & 1;
@@ -710,6 +730,7 @@ __device__ inline void blocked_strip(int64_t n, int64_t nev, const double* __res
             }
 
             if (!has_next) {
+                // the slot's last block: the whole window is final
 #pragma unroll
                 for (int q = 0; q < NT; ++q)
 #pragma unroll
