@@ -165,6 +165,31 @@ int trans_ev_tridi_to_band_adjoint_d(int64_t n, int nbw, int64_t nev,
                                      double *dv, double *dtau, int ckpt_every,
                                      void *work, size_t work_bytes, void *stream);
 
+/* The same adjoint in two halves, for callers (such as an autograd
+ * framework) that run the forward transformation anyway and keep the
+ * checkpoints until the backward pass instead of recomputing them:
+ *   trans_ev_tridi_to_band_fwd_ckpt_d  Z <- Q^* Z in place (the same result,
+ *       bitwise, as trans_ev_tridi_to_band_d) and writes the checkpoints
+ *       into `work`.  Arguments: 1 n, 2 nbw, 3 nev, 4 hh_v, 5 hh_tau, 6 Z,
+ *       7 ldz, 8 ckpt_every (0 or 16), 9 work, 10 work_bytes, 11 stream.
+ *   trans_ev_tridi_to_band_bwd_ckpt_d  G <- dL/dZ_in and dv, dtau from the
+ *       checkpoints a previous fwd_ckpt call with the same n, nbw, nev and
+ *       reflectors left in `work` (ordered before it on the stream; work
+ *       untouched in between).  Arguments: 1 n, 2 nbw, 3 nev, 4 hh_v,
+ *       5 hh_tau, 6 G, 7 ldg, 8 dv, 9 dtau, 10 ckpt_every, 11 work,
+ *       12 work_bytes, 13 stream.
+ * Workspace size: trbt_adjoint_workspace_bytes_d.  Same validation rules and
+ * status codes as the one-call adjoint. */
+int trans_ev_tridi_to_band_fwd_ckpt_d(int64_t n, int nbw, int64_t nev,
+                                      const double *hh_v, const double *hh_tau,
+                                      double *Z, int64_t ldz, int ckpt_every,
+                                      void *work, size_t work_bytes, void *stream);
+int trans_ev_tridi_to_band_bwd_ckpt_d(int64_t n, int nbw, int64_t nev,
+                                      const double *hh_v, const double *hh_tau,
+                                      double *G, int64_t ldg, double *dv, double *dtau,
+                                      int ckpt_every, void *work, size_t work_bytes,
+                                      void *stream);
+
 /* ------------------------------------------------------------------------
  * Batched back-transformation: many independent real problems of uneven
  * size (k-points, spin channels), each exactly the operation above, run

@@ -23,7 +23,8 @@ __all__ = [
     "TRBT_WORK_ALIGN", "TRBT_NBW_MAX", "trbt_problem_d", "trbt_plan_config",
     "trbt_plan_create_batched_d", "trbt_plan_exec", "trbt_plan_get_config", "trbt_plan_check",
     "trbt_plan_destroy", "BatchedPlan", "trbt_adjoint_workspace_bytes_d",
-    "trans_ev_tridi_to_band_adjoint_d", "adjoint", "BackTransform", "back_transform_autograd",
+    "trans_ev_tridi_to_band_adjoint_d", "trans_ev_tridi_to_band_fwd_ckpt_d",
+    "trans_ev_tridi_to_band_bwd_ckpt_d", "adjoint", "BackTransform", "back_transform_autograd",
 ]
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
@@ -73,6 +74,12 @@ def lib():
         L.trans_ev_tridi_to_band_adjoint_d.argtypes = [i64, i32, i64, vp, vp, vp, i64, vp, i64,
                                                        vp, vp, i32, vp, sz, vp]
         L.trans_ev_tridi_to_band_adjoint_d.restype = i32
+        L.trans_ev_tridi_to_band_fwd_ckpt_d.argtypes = [i64, i32, i64, vp, vp, vp, i64, i32, vp,
+                                                        sz, vp]
+        L.trans_ev_tridi_to_band_fwd_ckpt_d.restype = i32
+        L.trans_ev_tridi_to_band_bwd_ckpt_d.argtypes = [i64, i32, i64, vp, vp, vp, i64, vp, vp,
+                                                        i32, vp, sz, vp]
+        L.trans_ev_tridi_to_band_bwd_ckpt_d.restype = i32
         L.trbt_plan_create_batched_d.argtypes = [C.POINTER(trbt_problem_d), i32,
                                                  C.POINTER(trbt_plan_config),
                                                  C.POINTER(vp), vp]
@@ -327,6 +334,29 @@ def trans_ev_tridi_to_band_adjoint_d(n, nbw, nev, hh_v, hh_tau, Z_in, ldz, G, ld
         _ptr(dtau), ckpt_every, _ptr(work), work_bytes, _stream(stream))
 
 
+def trans_ev_tridi_to_band_fwd_ckpt_d(n, nbw, nev, hh_v, hh_tau, Z, ldz, ckpt_every, work,
+                                      work_bytes, stream=None) -> int:
+    return lib().trans_ev_tridi_to_band_fwd_ckpt_d(
+        n, nbw, nev, _ptr(hh_v), _ptr(hh_tau), _ptr(Z), ldz, ckpt_every, _ptr(work), work_bytes,
+        _stream(stream))
+
+
+def trans_ev_tridi_to_band_bwd_ckpt_d(n, nbw, nev, hh_v, hh_tau, G, ldg, dv, dtau, ckpt_every,
+                                      work, work_bytes, stream=None) -> int:
+    return lib().trans_ev_tridi_to_band_bwd_ckpt_d(
+        n, nbw, nev, _ptr(hh_v), _ptr(hh_tau), _ptr(G), ldg, _ptr(dv), _ptr(dtau), ckpt_every,
+        _ptr(work), work_bytes, _stream(stream))
+
+
+def _adjoint_workspace(n, nbw, nev, device):
+    import torch
+    nb = trbt_adjoint_workspace_bytes_d(n, nbw, nev)
+    if not nb:
+        return None, 0
+    buf = torch.empty(nb + TRBT_WORK_ALIGN, dtype=torch.uint8, device=device)
+    return buf[(-buf.data_ptr()) % TRBT_WORK_ALIGN:][:nb], nb
+
+
 def _colmajor(t):
     """(n, nev) tensor -> (a new buffer (nev, n) contiguous holding a copy of
     it, and the buffer's column-major (n, nev) view).  Always a copy: the
@@ -374,26 +404,43 @@ def _back_transform_function():
     class BackTransform(torch.autograd.Function):
         """Z_out = H_0 ... H_{K-1} Z_in (real) with the hand-written adjoint.
 
-        Saves only Z_in, hh_v and hh_tau; the backward pass recomputes the
-        forward states from checkpoints every 16 stages."""
+        The forward pass runs the checkpointing forward kernel and keeps its
+        workspace (a checkpoint every 16 stages, not the states in between)
+        for the backward pass, which recomputes the states inside each
+        16-stage block from it."""
 
         @staticmethod
         def forward(ctx, Z_in, hh_v, hh_tau, nbw):
-            zbuf, zin = _colmajor(Z_in.detach())
             obuf, out = _colmajor(Z_in.detach())
+            n, nev = out.shape
             v = hh_v.detach().contiguous()
             t = hh_tau.detach().contiguous()
-            back_transform(out, v, t, nbw)
-            ctx.save_for_backward(zbuf, v, t)
-            ctx.nbw = nbw
+            if v.dtype != torch.float64 or out.dtype != torch.float64:
+                raise TypeError("the differentiable back-transformation is real FP64")
+            work, nb = _adjoint_workspace(n, nbw, nev, out.device)
+            rc = trans_ev_tridi_to_band_fwd_ckpt_d(n, nbw, nev, v, t, out, max(n, 1), 16, work,
+                                                   nb)
+            if rc:
+                raise TrbtError(rc, "trans_ev_tridi_to_band_fwd_ckpt_d")
+            ctx.save_for_backward(v, t)
+            ctx.work, ctx.nb, ctx.nbw, ctx.shape = work, nb, nbw, (n, nev)
             return out
 
         @staticmethod
         def backward(ctx, grad_out):
-            zbuf, v, t = ctx.saved_tensors
+            v, t = ctx.saved_tensors
+            n, nev = ctx.shape
             gbuf, g = _colmajor(grad_out)
-            dz, dv, dt = adjoint(zbuf.t(), g, v, t, ctx.nbw)
-            return dz, dv, dt, None
+            K = v.shape[0]
+            dv = torch.empty(max(K, 1), ctx.nbw, dtype=torch.float64, device=v.device)[:K]
+            dt = torch.empty(max(K, 1), dtype=torch.float64, device=v.device)[:K]
+            rc = trans_ev_tridi_to_band_bwd_ckpt_d(n, ctx.nbw, nev, v, t, g, max(n, 1),
+                                                   dv if K else None, dt if K else None, 16,
+                                                   ctx.work, ctx.nb)
+            if rc:
+                raise TrbtError(rc, "trans_ev_tridi_to_band_bwd_ckpt_d")
+            ctx.work = None
+            return g, dv, dt, None
 
     return BackTransform
 

@@ -107,7 +107,7 @@ __global__ __launch_bounds__(256) void k_pack_adj(int64_t n, const double* __res
 template <int NB, int NW>
 __global__ __launch_bounds__(64 * NW) void k_blocked_ckpt(int64_t n, int64_t nev,
                                                           const double* __restrict__ blocks,
-                                                          double* __restrict__ Zs,
+                                                          double* __restrict__ Z, int64_t ldz,
                                                           double* __restrict__ ckpt,
                                                           unsigned* __restrict__ err)
 {
@@ -115,7 +115,7 @@ __global__ __launch_bounds__(64 * NW) void k_blocked_ckpt(int64_t n, int64_t nev
     if (threadIdx.x < NW) prog[threadIdx.x] = 0;
     __syncthreads();
     blocked_strip<NB, 1, false, ring_depth<NB, false>(), NW, true>(
-        n, nev, blocks, Zs, n, err, blockIdx.x, prog, ckpt, gridDim.x);
+        n, nev, blocks, Z, ldz, err, blockIdx.x, prog, ckpt, gridDim.x);
 }
 
 // Order the LDS writes of this wave before its following LDS reads.
@@ -148,7 +148,6 @@ __global__ __launch_bounds__(64 * NW) void k_adj_blocked(int64_t n, int64_t nev,
     const int64_t strip = blockIdx.x, nstrips = gridDim.x;
     const int64_t nblk = (n - 2 + KB - 1) / KB;
     const int64_t J = sweeps_in_stage(n, NB, 0);
-    const int64_t nblocks = slot_base(J, nblk, nt1);
     const int64_t col = strip * 16 + (lane & 15);
     const bool cols_inside = (strip + 1) * 16 <= nev;
     const int rsub = lane >> 4, cl = lane & 15;
@@ -202,7 +201,7 @@ __global__ __launch_bounds__(64 * NW) void k_adj_blocked(int64_t n, int64_t nev,
                 Gt = mfma(pk[A::ST_OFF + u * 64 + lane], Bt[u], Gt);
                 Y = mfma(pk[A::TT_OFF + u * 64 + lane], Bt[u], Y);
             }
-            double* __restrict__ pp = part + ((size_t)strip * nblocks + b) * A::PPB;
+            double* __restrict__ pp = part + ((size_t)b * nstrips + strip) * A::PPB;
             {   // dtau_p partial: -sum over the strip's columns of g_p w_p
                 double pr[4];
 #pragma unroll
@@ -288,8 +287,8 @@ __global__ __launch_bounds__(64 * NW) void k_adj_blocked(int64_t n, int64_t nev,
     }
 }
 
-// Finishing pass: one workgroup per block.  Sums the strips' partials in
-// strip order, applies the column-independent corrections and writes dv and
+// Finishing pass: one workgroup per block.  Sums the strips' partials in a
+// fixed order, applies the column-independent corrections and writes dv and
 // dtau of the block's reflectors.
 template <int NB>
 __global__ __launch_bounds__(256) void k_adj_finish(int64_t n, int64_t nstrips,
@@ -310,7 +309,6 @@ __global__ __launch_bounds__(256) void k_adj_finish(int64_t n, int64_t nstrips,
     const int64_t b = blockIdx.x;
     const int64_t nblk = (n - 2 + KB - 1) / KB;
     const int64_t J = sweeps_in_stage(n, NB, 0);
-    const int64_t nblocks = slot_base(J, nblk, nt1);
     if (tid == 0) {
         int64_t lo = 0, hi = J;
         while (hi - lo > 1) {
@@ -321,9 +319,18 @@ __global__ __launch_bounds__(256) void k_adj_finish(int64_t n, int64_t nstrips,
         s_t = lo * nt1 + (b - slot_base(lo, nblk, nt1));
     }
     const double* pk = apk + (size_t)b * A::APB;
+    // the block's partials from all strips are contiguous: [strip][PPB]
+    const double* __restrict__ pb = part + (size_t)b * nstrips * A::PPB;
     for (int idx = tid; idx < A::DT_OFF + 16; idx += 256) {
-        double acc = 0.0;
-        for (int64_t s = 0; s < nstrips; ++s) acc += part[((size_t)s * nblocks + b) * A::PPB + idx];
+        // eight running sums (strip s into sum s % 8), combined in a fixed
+        // order: many loads in flight, the same result on every run
+        double a8[8] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+        int64_t s = 0;
+        for (; s + 8 <= nstrips; s += 8)
+#pragma unroll
+            for (int k = 0; k < 8; ++k) a8[k] += pb[(size_t)(s + k) * A::PPB + idx];
+        for (int k = 0; s < nstrips; ++s, ++k) a8[k] += pb[(size_t)s * A::PPB + idx];
+        const double acc = ((a8[0] + a8[1]) + (a8[2] + a8[3])) + ((a8[4] + a8[5]) + (a8[6] + a8[7]));
         if (idx < A::DT_OFF) {
             const int which = idx / A::P2_OFF, rem = idx % A::P2_OFF;
             const int q = rem / 256, e = (rem % 256) / 64, l = rem % 64;
@@ -434,12 +441,12 @@ __device__ inline void apply_real(double* z, const double* __restrict__ v, doubl
 __global__ __launch_bounds__(64) void k_adj_stream_fwd(int64_t n, int nbw, int64_t nev,
                                                        const double* __restrict__ hv,
                                                        const double* __restrict__ ht,
-                                                       double* __restrict__ Zs,
+                                                       double* __restrict__ Z, int64_t ldz,
                                                        double* __restrict__ ck)
 {
     const int64_t c = (int64_t)blockIdx.x * 64 + threadIdx.x;
     if (c >= nev) return;
-    double* z = Zs + c * n;
+    double* z = Z + c * ldz;
     const int64_t nblk = (n - 2 + KB - 1) / KB;
     int64_t cb = 0;
     for (int64_t t = 0; t < nblk; ++t) {
@@ -662,26 +669,85 @@ int adj_validate(int64_t n, int nbw, int64_t nev, const double* hv, const double
     return TRBT_SUCCESS;
 }
 
+// The adjoint in two halves.  adj_forward: the forward transformation of Z
+// (in place) that also writes the checkpoints into the workspace;
+// adj_backward: the reverse sweep from those checkpoints.
 template <int NB>
-void launch_blocked_adjoint(int64_t n, int64_t nev, const double* hv, const double* ht,
-                            double* G, int64_t ldg, double* dv, double* dtau, char* ws,
-                            const AdjLayout& L, hipStream_t st)
+void blocked_forward(int64_t n, int64_t nev, const double* hv, const double* ht, double* Z,
+                     int64_t ldz, char* ws, const AdjLayout& L, hipStream_t st)
 {
-    unsigned* err = (unsigned*)ws;
-    double* Zs = (double*)(ws + L.zs);
     double* fwd = (double*)(ws + L.fwd);
-    double* apk = (double*)(ws + L.apk);
-    double* ck = (double*)(ws + L.ckpt);
-    double* part = (double*)(ws + L.part);
     const unsigned nb = (unsigned)L.nblocks, ns = (unsigned)L.nstrips;
     hipLaunchKernelGGL((k_pack<NB, false>), dim3(nb), dim3(256), 0, st, n, hv, ht, fwd);
     hipLaunchKernelGGL((k_blocked_ckpt<NB, ADJ_WAVES>), dim3(ns), dim3(64 * ADJ_WAVES), 0, st, n,
-                       nev, (const double*)fwd, Zs, ck, err);
+                       nev, (const double*)fwd, Z, ldz, (double*)(ws + L.ckpt), (unsigned*)ws);
+}
+
+template <int NB>
+void blocked_backward(int64_t n, int64_t nev, const double* hv, const double* ht, double* G,
+                      int64_t ldg, double* dv, double* dtau, char* ws, const AdjLayout& L,
+                      hipStream_t st)
+{
+    double* apk = (double*)(ws + L.apk);
+    double* part = (double*)(ws + L.part);
+    const unsigned nb = (unsigned)L.nblocks, ns = (unsigned)L.nstrips;
     hipLaunchKernelGGL((k_pack_adj<NB>), dim3(nb), dim3(256), 0, st, n, hv, ht, apk);
     hipLaunchKernelGGL((k_adj_blocked<NB, ADJ_WAVES>), dim3(ns), dim3(64 * ADJ_WAVES), 0, st, n,
-                       nev, (const double*)apk, (const double*)ck, G, ldg, part, err);
+                       nev, (const double*)apk, (const double*)(ws + L.ckpt), G, ldg, part,
+                       (unsigned*)ws);
     hipLaunchKernelGGL((k_adj_finish<NB>), dim3(nb), dim3(256), 0, st, n, (int64_t)ns,
                        (const double*)apk, (const double*)part, dv, dtau);
+}
+
+int adj_forward(int64_t n, int nbw, int64_t nev, const double* hv, const double* ht, double* Z,
+                int64_t ldz, char* ws, const AdjLayout& L, hipStream_t st)
+{
+    if (use_blocked(n, nbw, false)) {
+        switch (nbw) {
+            case 16: blocked_forward<16>(n, nev, hv, ht, Z, ldz, ws, L, st); break;
+            case 32: blocked_forward<32>(n, nev, hv, ht, Z, ldz, ws, L, st); break;
+            case 48: blocked_forward<48>(n, nev, hv, ht, Z, ldz, ws, L, st); break;
+            case 64: blocked_forward<64>(n, nev, hv, ht, Z, ldz, ws, L, st); break;
+            default: return TRBT_ERR_INTERNAL;
+        }
+    } else {
+        hipLaunchKernelGGL(k_adj_stream_fwd, dim3((unsigned)L.nwaves), dim3(64), 0, st, n, nbw,
+                           nev, hv, ht, Z, ldz, (double*)(ws + L.ckpt));
+    }
+    return hipGetLastError() == hipSuccess ? TRBT_SUCCESS : TRBT_ERR_HIP;
+}
+
+int adj_backward(int64_t n, int nbw, int64_t nev, const double* hv, const double* ht,
+                 double* G, int64_t ldg, double* dv, double* dtau, char* ws, const AdjLayout& L,
+                 hipStream_t st)
+{
+    if (use_blocked(n, nbw, false)) {
+        switch (nbw) {
+            case 16: blocked_backward<16>(n, nev, hv, ht, G, ldg, dv, dtau, ws, L, st); break;
+            case 32: blocked_backward<32>(n, nev, hv, ht, G, ldg, dv, dtau, ws, L, st); break;
+            case 48: blocked_backward<48>(n, nev, hv, ht, G, ldg, dv, dtau, ws, L, st); break;
+            case 64: blocked_backward<64>(n, nev, hv, ht, G, ldg, dv, dtau, ws, L, st); break;
+            default: return TRBT_ERR_INTERNAL;
+        }
+    } else {
+        const int64_t K = num_reflectors(n, nbw);
+        const unsigned nw = (unsigned)L.nwaves;
+        hipLaunchKernelGGL(k_adj_stream_bwd, dim3(nw), dim3(64), 0, st, n, nbw, nev, hv, ht,
+                           (double*)(ws + L.zs), (const double*)(ws + L.ckpt),
+                           (double*)(ws + L.tape), G, ldg, (double*)(ws + L.part), K);
+        const int64_t cnt = K * (nbw + 1);
+        hipLaunchKernelGGL(k_adj_stream_finish, dim3((unsigned)((cnt + 255) / 256)), dim3(256), 0,
+                           st, n, nbw, K, L.nwaves, (const double*)(ws + L.part), dv, dtau);
+    }
+    return hipGetLastError() == hipSuccess ? TRBT_SUCCESS : TRBT_ERR_HIP;
+}
+
+int zero_grads(int64_t K, int nbw, double* dv, double* dtau, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_fill_zero, dim3((unsigned)((K * nbw + 255) / 256)), dim3(256), 0, st, dv,
+                       K * nbw);
+    hipLaunchKernelGGL(k_fill_zero, dim3((unsigned)((K + 255) / 256)), dim3(256), 0, st, dtau, K);
+    return hipGetLastError() == hipSuccess ? TRBT_SUCCESS : TRBT_ERR_HIP;
 }
 
 }  // namespace
@@ -714,44 +780,73 @@ int trans_ev_tridi_to_band_adjoint_d(int64_t n, int nbw, int64_t nev, const doub
     rc = check_device();
     if (rc) return rc;
     hipStream_t st = (hipStream_t)stream;
-    if (nev == 0) {
-        hipLaunchKernelGGL(k_fill_zero, dim3((unsigned)((K * nbw + 255) / 256)), dim3(256), 0,
-                           st, dv, K * nbw);
-        hipLaunchKernelGGL(k_fill_zero, dim3((unsigned)((K + 255) / 256)), dim3(256), 0, st,
-                           dtau, K);
-        return hipGetLastError() == hipSuccess ? TRBT_SUCCESS : TRBT_ERR_HIP;
-    }
+    if (nev == 0) return zero_grads(K, nbw, dv, dtau, st);
     const AdjLayout L = adj_layout(n, nbw, nev);
     if (!work || work_bytes < L.total) return TRBT_ERR_WORKSPACE;
     char* ws = (char*)work;
     hipLaunchKernelGGL(k_zero_words, dim3(1), dim3(64), 0, st, (unsigned*)work, 64);
-    if (hipMemcpy2DAsync(ws + L.zs, (size_t)n * sizeof(double), Z_in, (size_t)ldz * sizeof(double),
+    double* Zs = (double*)(ws + L.zs);
+    if (hipMemcpy2DAsync(Zs, (size_t)n * sizeof(double), Z_in, (size_t)ldz * sizeof(double),
                          (size_t)n * sizeof(double), (size_t)nev, hipMemcpyDeviceToDevice,
                          st) != hipSuccess)
         return TRBT_ERR_HIP;
-    if (use_blocked(n, nbw, false)) {
-        switch (nbw) {
-            case 16: launch_blocked_adjoint<16>(n, nev, hh_v, hh_tau, G, ldg, dv, dtau, ws, L, st); break;
-            case 32: launch_blocked_adjoint<32>(n, nev, hh_v, hh_tau, G, ldg, dv, dtau, ws, L, st); break;
-            case 48: launch_blocked_adjoint<48>(n, nev, hh_v, hh_tau, G, ldg, dv, dtau, ws, L, st); break;
-            case 64: launch_blocked_adjoint<64>(n, nev, hh_v, hh_tau, G, ldg, dv, dtau, ws, L, st); break;
-            default: return TRBT_ERR_INTERNAL;
-        }
-    } else {
-        double* Zs = (double*)(ws + L.zs);
-        double* ck = (double*)(ws + L.ckpt);
-        double* tape = (double*)(ws + L.tape);
-        double* part = (double*)(ws + L.part);
-        const unsigned nw = (unsigned)L.nwaves;
-        hipLaunchKernelGGL(k_adj_stream_fwd, dim3(nw), dim3(64), 0, st, n, nbw, nev, hh_v, hh_tau,
-                           Zs, ck);
-        hipLaunchKernelGGL(k_adj_stream_bwd, dim3(nw), dim3(64), 0, st, n, nbw, nev, hh_v,
-                           hh_tau, Zs, (const double*)ck, tape, G, ldg, part, K);
-        const int64_t cnt = K * (nbw + 1);
-        hipLaunchKernelGGL(k_adj_stream_finish, dim3((unsigned)((cnt + 255) / 256)), dim3(256), 0,
-                           st, n, nbw, K, L.nwaves, (const double*)part, dv, dtau);
-    }
-    return hipGetLastError() == hipSuccess ? TRBT_SUCCESS : TRBT_ERR_HIP;
+    rc = adj_forward(n, nbw, nev, hh_v, hh_tau, Zs, n, ws, L, st);
+    if (rc) return rc;
+    return adj_backward(n, nbw, nev, hh_v, hh_tau, G, ldg, dv, dtau, ws, L, st);
+}
+
+int trans_ev_tridi_to_band_fwd_ckpt_d(int64_t n, int nbw, int64_t nev, const double* hh_v,
+                                      const double* hh_tau, double* Z, int64_t ldz,
+                                      int ckpt_every, void* work, size_t work_bytes, void* stream)
+{
+    if (n < 0) return -1;
+    if (nbw < 1 || nbw > TRBT_NBW_MAX) return -2;
+    if (nev < 0 || nev > n) return -3;
+    const int64_t K = num_reflectors(n, nbw);
+    const bool active = K > 0 && nev > 0;
+    if (active && !hh_v) return -4;
+    if (active && !hh_tau) return -5;
+    if (active && !Z) return -6;
+    if (ldz < (n > 1 ? n : 1)) return -7;
+    if (ckpt_every != 0 && ckpt_every != 16) return -8;
+    if (work && ((uintptr_t)work % TRBT_WORK_ALIGN)) return -9;
+    if (work_bytes && !work) return -9;
+    if (!active) return TRBT_SUCCESS;
+    int rc = check_device();
+    if (rc) return rc;
+    const AdjLayout L = adj_layout(n, nbw, nev);
+    if (!work || work_bytes < L.total) return TRBT_ERR_WORKSPACE;
+    hipStream_t st = (hipStream_t)stream;
+    hipLaunchKernelGGL(k_zero_words, dim3(1), dim3(64), 0, st, (unsigned*)work, 64);
+    return adj_forward(n, nbw, nev, hh_v, hh_tau, Z, ldz, (char*)work, L, st);
+}
+
+int trans_ev_tridi_to_band_bwd_ckpt_d(int64_t n, int nbw, int64_t nev, const double* hh_v,
+                                      const double* hh_tau, double* G, int64_t ldg, double* dv,
+                                      double* dtau, int ckpt_every, void* work,
+                                      size_t work_bytes, void* stream)
+{
+    if (n < 0) return -1;
+    if (nbw < 1 || nbw > TRBT_NBW_MAX) return -2;
+    if (nev < 0 || nev > n) return -3;
+    const int64_t K = num_reflectors(n, nbw);
+    if (K > 0 && !hh_v) return -4;
+    if (K > 0 && !hh_tau) return -5;
+    if (K > 0 && nev > 0 && !G) return -6;
+    if (ldg < (n > 1 ? n : 1)) return -7;
+    if (K > 0 && !dv) return -8;
+    if (K > 0 && !dtau) return -9;
+    if (ckpt_every != 0 && ckpt_every != 16) return -10;
+    if (work && ((uintptr_t)work % TRBT_WORK_ALIGN)) return -11;
+    if (work_bytes && !work) return -11;
+    if (K == 0) return TRBT_SUCCESS;
+    int rc = check_device();
+    if (rc) return rc;
+    hipStream_t st = (hipStream_t)stream;
+    if (nev == 0) return zero_grads(K, nbw, dv, dtau, st);
+    const AdjLayout L = adj_layout(n, nbw, nev);
+    if (!work || work_bytes < L.total) return TRBT_ERR_WORKSPACE;
+    return adj_backward(n, nbw, nev, hh_v, hh_tau, G, ldg, dv, dtau, (char*)work, L, st);
 }
 
 }  // extern "C"

@@ -179,3 +179,47 @@ def test_adjoint_validation_codes(T):
         with pytest.raises(T.TrbtError) as e:
             T.trbt_adjoint_workspace_bytes_d(*bad)
         assert e.value.status == code
+
+
+def test_split_adjoint_validation_codes(T):
+    """The checkpointing forward and the backward-from-checkpoints entries
+    validate on the host, in argument order, before any HIP call."""
+    fw = T.trans_ev_tridi_to_band_fwd_ckpt_d
+    okf = dict(n=100, nbw=32, nev=10, hv=FAKE, ht=FAKE, Z=FAKE, ldz=100, ck=16, work=None, wb=0)
+
+    def callf(**kw):
+        a = dict(okf, **kw)
+        return fw(a["n"], a["nbw"], a["nev"], a["hv"], a["ht"], a["Z"], a["ldz"], a["ck"],
+                  a["work"], a["wb"], 0)
+
+    assert callf(n=-1) == -1
+    assert callf(nbw=300) == -2
+    assert callf(nev=-2) == -3
+    assert callf(hv=None) == -4
+    assert callf(ht=None) == -5
+    assert callf(Z=None) == -6
+    assert callf(ldz=10) == -7
+    assert callf(ck=32) == -8
+    assert callf(work=FAKE + 4) == -9
+    assert callf(nev=0, hv=None, ht=None, Z=None) == 0
+    bw = T.trans_ev_tridi_to_band_bwd_ckpt_d
+    okb = dict(n=100, nbw=32, nev=10, hv=FAKE, ht=FAKE, G=FAKE, ldg=100, dv=FAKE, dt=FAKE, ck=16,
+               work=None, wb=0)
+
+    def callb(**kw):
+        a = dict(okb, **kw)
+        return bw(a["n"], a["nbw"], a["nev"], a["hv"], a["ht"], a["G"], a["ldg"], a["dv"],
+                  a["dt"], a["ck"], a["work"], a["wb"], 0)
+
+    assert callb(n=-1) == -1
+    assert callb(nbw=0) == -2
+    assert callb(nev=101) == -3
+    assert callb(hv=None) == -4
+    assert callb(ht=None) == -5
+    assert callb(G=None) == -6
+    assert callb(ldg=99) == -7
+    assert callb(dv=None) == -8
+    assert callb(dt=None) == -9
+    assert callb(ck=1) == -10
+    assert callb(work=None, wb=8) == -11
+    assert callb(nbw=1, hv=None, ht=None, dv=None, dt=None) == 0

@@ -297,3 +297,47 @@ def test_c5_full_size_properties(oracle_mod):
           - _gpu_loss(Z, G, V - h * dV, tau - h * dT, nbw)) / (2 * h)
     an = np.sum(dv * dV) + np.sum(dt * dT)
     assert abs(fd - an) <= 1e-6 * max(abs(an), 1.0), (fd, an)
+
+
+@pytest.mark.parametrize("n,nbw,nev", [(301, 64, 63), (150, 32, 40), (90, 8, 31), (100, 24, 17)])
+def test_split_adjoint(oracle_mod, n, nbw, nev):
+    """Checkpointing forward + backward from the checkpoints: the forward
+    result is bitwise the plain forward call's, the gradients bitwise the
+    one-call adjoint's, and both match the oracle."""
+    import paper_2002_10991_amd as T
+    torch = _torch()
+    Z, G, V, tau = _inputs(n, nbw, nev, 333 + n)
+    print(f"[gpu] split adjoint n={n} nbw={nbw} nev={nev}", flush=True)
+    Vd = torch.from_numpy(V).to("cuda")
+    td = torch.from_numpy(tau).to("cuda")
+    zb = torch.from_numpy(np.ascontiguousarray(Z.T)).to("cuda")
+    gb = torch.from_numpy(np.ascontiguousarray(G.T)).to("cuda")
+    K = len(tau)
+    dv = torch.empty(K, nbw, dtype=torch.float64, device="cuda")
+    dt = torch.empty(K, dtype=torch.float64, device="cuda")
+    nb = T.trbt_adjoint_workspace_bytes_d(n, nbw, nev)
+    w = torch.empty(nb + 256, dtype=torch.uint8, device="cuda")
+    w = w[(-w.data_ptr()) % 256:][:nb]
+    assert T.trans_ev_tridi_to_band_fwd_ckpt_d(n, nbw, nev, Vd, td, zb, n, 16, w, nb) == 0
+    assert T.trans_ev_tridi_to_band_bwd_ckpt_d(n, nbw, nev, Vd, td, gb, n, dv, dt, 16, w, nb) == 0
+    torch.cuda.synchronize()
+    assert int(w[:4].view(torch.int32).cpu()[0]) == 0
+    fwd_plain, _ = _plain_forward(Z, V, tau, nbw)
+    assert np.array_equal(zb.cpu().numpy(), fwd_plain)
+    one = gpu_adjoint(Z, G, V, tau, nbw)
+    assert np.array_equal(gb.cpu().numpy(), one[0][:nev, :n])
+    assert np.array_equal(dv.cpu().numpy(), one[2])
+    assert np.array_equal(dt.cpu().numpy(), one[3])
+    rZ, rv, rt = oracle_mod.adjoint(Z, G, V, tau, nbw)
+    assert _relerr(gb.cpu().numpy().T, rZ) <= TOL
+    assert _relerr(dv.cpu().numpy(), rv) <= TOL
+    assert _relerr(dt.cpu().numpy(), rt) <= TOL
+
+
+def _plain_forward(Z, V, tau, nbw):
+    import paper_2002_10991_amd as T
+    torch = _torch()
+    zb = torch.from_numpy(np.ascontiguousarray(Z.T)).to("cuda")
+    T.back_transform(zb.T, torch.from_numpy(V).to("cuda"), torch.from_numpy(tau).to("cuda"), nbw)
+    torch.cuda.synchronize()
+    return zb.cpu().numpy(), None
