@@ -111,11 +111,11 @@ __global__ __launch_bounds__(64 * NW) void k_blocked_ckpt(int64_t n, int64_t nev
                                                           double* __restrict__ ckpt,
                                                           unsigned* __restrict__ err)
 {
-    __shared__ int prog[NW];
-    if (threadIdx.x < NW) prog[threadIdx.x] = 0;
+    __shared__ StripLds<NB, 1, false, NW> S;
+    S.reset();
     __syncthreads();
     blocked_strip<NB, 1, false, ring_depth<NB, false>(), NW, true>(
-        n, nev, blocks, Z, ldz, err, blockIdx.x, prog, ckpt, gridDim.x);
+        n, nev, blocks, Z, ldz, err, blockIdx.x, S, ckpt, gridDim.x);
 }
 
 // Order the LDS writes of this wave before its following LDS reads.

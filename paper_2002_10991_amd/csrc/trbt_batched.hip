@@ -96,7 +96,7 @@ __global__ __launch_bounds__(64 * NW) void k_blocked_batched(const BProb* __rest
                                                              unsigned* __restrict__ err)
 {
     constexpr int D = ring_depth<NB, false>();
-    __shared__ int prog[NW];
+    __shared__ StripLds<NB, CT, false, NW> S;
     __shared__ int s_task;
     const int home = blockIdx.x % NXCD;
     for (;;) {
@@ -114,13 +114,13 @@ __global__ __launch_bounds__(64 * NW) void k_blocked_batched(const BProb* __rest
             }
             s_task = task;
         }
-        if (threadIdx.x < NW) prog[threadIdx.x] = 0;
+        S.reset();
         __syncthreads();
         const int task = s_task;
         if (task < 0) return;
         const BTask tk = tasks[task];
         const BProb& P = probs[tk.prob];
-        blocked_strip<NB, CT, false, D, NW>(P.n, P.nev, P.ws, P.Z, P.ldz, err, tk.strip, prog);
+        blocked_strip<NB, CT, false, D, NW>(P.n, P.nev, P.ws, P.Z, P.ldz, err, tk.strip, S);
         __syncthreads();
     }
 }

@@ -520,6 +520,61 @@ __device__ inline void load_chunk(__amdgpu_buffer_rsrc_t r, uint32_t boff, int c
     if constexpr (CPLX) im[slot] = buffer_load_f64(r, lane * 8 + 512, soff);
 }
 
+// Per-workgroup LDS state of the strip pipeline.
+//   prog[w]      blocks finished by wave w (slot-sequence encoding)
+//   written[w]   hand-off tiles wave w has put into its exchange ring
+//   consumed[w]  hand-off tiles of wave w's ring that wave w+1 has taken
+//   ring[w][R]   wave w -> wave w+1 exchange ring of retired bottom tiles
+// Consecutive waves of a workgroup hold consecutive slots of one round, so
+// most hand-off tiles travel through LDS; only each slot's first NT retired
+// tiles (the next slot's initial window), the slot's last block and the
+// last wave's tiles (read by wave 0 in the next round) go through Z.
+// LDS traffic counts in lgkmcnt, so it never holds up the waits for the
+// operand stream the way a global store does (stores count in vmcnt).
+template <int NB, int CT, bool CPLX, int NW>
+struct StripLds {
+    static constexpr int R = 3;                              // tiles per ring
+    static constexpr int TD = 256 * (CPLX ? 2 : 1) * CT;     // doubles per tile set
+    int prog[NW];
+    int written[NW];
+    int consumed[NW];
+    double ring[NW > 1 ? NW - 1 : 1][R][TD];
+    __device__ void reset()
+    {
+        if (threadIdx.x < NW) {
+            prog[threadIdx.x] = 0;
+            written[threadIdx.x] = 0;
+            consumed[threadIdx.x] = 0;
+        }
+    }
+};
+
+template <bool CPLX, int CT>
+__device__ inline void lds_put(double* __restrict__ dst, const Tile<CPLX> (&t)[CT], int lane)
+{
+    constexpr int NC = CPLX ? 2 : 1;
+#pragma unroll
+    for (int c = 0; c < CT; ++c)
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+            dst[((c * NC) * 4 + e) * 64 + lane] = t[c].re[e];
+            if constexpr (CPLX) dst[((c * NC + 1) * 4 + e) * 64 + lane] = t[c].im[e];
+        }
+}
+
+template <bool CPLX, int CT>
+__device__ inline void lds_get(Tile<CPLX> (&t)[CT], const double* __restrict__ src, int lane)
+{
+    constexpr int NC = CPLX ? 2 : 1;
+#pragma unroll
+    for (int c = 0; c < CT; ++c)
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+            t[c].re[e] = src[((c * NC) * 4 + e) * 64 + lane];
+            if constexpr (CPLX) t[c].im[e] = src[((c * NC + 1) * 4 + e) * 64 + lane];
+        }
+}
+
 // Main blocked kernel.  Per block the operand stream is consumed in order:
 //   chunks 0 .. 4NT-1       A1 chunk (q, u) = (c/4, c%4):   Y += A1 * Zwin
 //   chunks 4NT .. 8NT-1     -V chunk (u, q), u ascending, q descending:
@@ -541,9 +596,13 @@ __device__ inline void load_chunk(__amdgpu_buffer_rsrc_t r, uint32_t boff, int c
 template <int NB, int CT, bool CPLX, int D, int NW, bool CKPT = false>
 __device__ inline void blocked_strip(int64_t n, int64_t nev, const double* __restrict__ wsb,
                                      double* __restrict__ Z, int64_t ldz,
-                                     unsigned* __restrict__ err, int64_t strip, int* prog,
+                                     unsigned* __restrict__ err, int64_t strip,
+                                     StripLds<NB, CT, CPLX, NW>& S,
                                      double* __restrict__ ckpt = nullptr, int64_t nstrips = 0)
 {
+    constexpr int XR = StripLds<NB, CT, CPLX, NW>::R;
+    int* prog = S.prog;
+    int xput = 0, xget = 0;   // exchange tiles this wave has put / taken so far
     static_assert(!CKPT || (CT == 1 && !CPLX), "checkpoints: real, one 16-column tile");
     using G = Geo<NB, CPLX>;
     constexpr int NT = G::NT;
@@ -596,9 +655,17 @@ __device__ inline void blocked_strip(int64_t n, int64_t nev, const double* __res
                     for (int e = 0; e < 4; ++e)
                         cp[(size_t)q * nstrips * 256 + e * 64] = zt[q][0].re[e];
             }
-            // the top tile of the next block: slot j-1 must have retired it
+            // the top tile of the next block: slot j-1 must have retired it.
+            // From wave w-1's exchange ring when it put it there (slot j-1 is
+            // in the same round and this is not the tile of its last block),
+            // else from Z.
             Tile<CPLX> znext[CT];
-            if (has_next) {
+            const bool xin = has_next && w > 0 && t + 2 < nblk;
+            if (xin) {
+                if (!wait_progress(S.written, w - 1, xget + 1, err, lane)) return;
+                lds_get<CPLX, CT>(znext, &S.ring[w - 1][xget % XR][0], lane);
+                ++xget;
+            } else if (has_next) {
                 if (j > 0 && !wait_progress(prog, wprev, need0 + (int)t + 2, err, lane)) return;
                 const bool inside = cols_inside && p0 - 16 >= 0 && p0 <= n;
 #pragma unroll
@@ -621,8 +688,22 @@ __device__ inline void blocked_strip(int64_t n, int64_t nev, const double* __res
                     load_chunk<CPLX, D>(ops, boff + G::PB * sizeof(double), c + D - NCH, lane,
                                         ring_re, ring_im, slot);
             };
+            bool xfail = false;
             auto store_bottom = [&]() {   // the retiring tile, once it is final
-                if (has_next) {
+                if (!has_next) return;
+                // to wave w+1 through LDS: slot j+1 exists, is in this round, and
+                // this is not one of the first NT tiles (its initial window)
+                const bool xout = w < NW - 1 && j + 1 < J && t >= t0 + NT;
+                if (xout) {
+                    if (!wait_progress(S.consumed, w, xput - XR + 1, err, lane)) {
+                        xfail = true;
+                        return;
+                    }
+                    lds_put<CPLX, CT>(&S.ring[w][xput % XR][0], zsh[NT], lane);
+                    ++xput;
+                    __hip_atomic_store(&S.written[w], xput, __ATOMIC_RELEASE,
+                                       __HIP_MEMORY_SCOPE_WORKGROUP);
+                } else {
                     const int64_t rb = p0 + 16 * (NT - 1);
                     const bool inside = cols_inside && rb >= 0 && rb + 16 <= n;
 #pragma unroll
@@ -729,6 +810,7 @@ __device__ inline void blocked_strip(int64_t n, int64_t nev, const double* __res
                 }
             }
 
+            if (xfail) return;
             if (!has_next) {
                 // the slot's last block: the whole window is final
 #pragma unroll
@@ -738,6 +820,9 @@ __device__ inline void blocked_strip(int64_t n, int64_t nev, const double* __res
                         store_tile<CPLX>(zsh[q + 1][c], Z, ldz, n, nev, p0 + 16 * q + rsub,
                                          col_base + 16 * c);
             }
+            if (xin)   // the exchange tile read at the start of this block is in registers
+                __hip_atomic_store(&S.consumed[w - 1], xget, __ATOMIC_RELEASE,
+                                   __HIP_MEMORY_SCOPE_WORKGROUP);
             __hip_atomic_store(&prog[w], (int)(j * (nblk + 1) + t + 1), __ATOMIC_RELEASE,
                                __HIP_MEMORY_SCOPE_WORKGROUP);
             if (has_next) {
@@ -758,11 +843,11 @@ __global__ __launch_bounds__(64 * NW) void k_blocked(int64_t n, int64_t nev,
                                                      double* __restrict__ Z, int64_t ldz,
                                                      unsigned* __restrict__ err)
 {
-    __shared__ int prog[NW];
-    if (threadIdx.x < NW) prog[threadIdx.x] = 0;
+    __shared__ StripLds<NB, CT, CPLX, NW> S;
+    S.reset();
     __syncthreads();
     blocked_strip<NB, CT, CPLX, D, NW>(n, nev, ws + HDR_BYTES / sizeof(double), Z, ldz, err,
-                                       blockIdx.x, prog);
+                                       blockIdx.x, S);
 }
 
 __global__ void k_zero_words(unsigned* p, int count)
