@@ -95,7 +95,7 @@ __global__ __launch_bounds__(64 * NW) void k_blocked_batched(const BProb* __rest
                                                              int* __restrict__ qnext,
                                                              unsigned* __restrict__ err)
 {
-    constexpr int D = ring_depth<NB, false>();
+    constexpr int D = ring_depth<NB, false, CT>();
     __shared__ StripLds<NB, CT, false, NW> S;
     __shared__ int s_task;
     const int home = blockIdx.x % NXCD;

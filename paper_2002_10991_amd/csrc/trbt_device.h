@@ -488,11 +488,14 @@ __device__ inline bool wait_progress(int* prog, int idx, int need, unsigned* err
 
 // Operand ring depth (chunks loaded ahead of use).  The ring position of a
 // chunk is its index in the block's stream modulo D, and the ring runs on
-// into the next block, so D must divide the chunk count per block.
-template <int NB, bool CPLX>
+// into the next block, so D must divide the chunk count per block.  Real
+// blocks with one column tile (one MFMA per chunk) read a whole block ahead,
+// with two tiles half a block; complex blocks (three MFMAs per chunk, two
+// registers per slot) 8 chunks.
+template <int NB, bool CPLX, int CT = 1>
 __host__ __device__ constexpr int ring_depth()
 {
-    return CPLX ? 8 : 4 * Geo<NB, CPLX>::NT;
+    return CPLX ? 8 : (CT == 1 ? 8 : 4) * Geo<NB, CPLX>::NT;
 }
 
 // Operand chunks are read through a buffer resource holding the slot's
