@@ -197,11 +197,15 @@ struct Geo {
 //   A1[p][r] = sum_{q>=p} T[p][q] conj(Vt[r][q])
 // Packed for v_mfma_f64_16x16x4_f64 (A operand: lane i+16k holds A[i][k];
 // B operand: lane j+16k holds B[k][j]; accumulator: lane j+16g holds rows
-// g, g+4, g+8, g+12 of column j), chunk (q, u):
-//   A1 chunk lane l: A1[l%16][16q + 4u + l/16]     stored at position 4q+u
+// g, g+4, g+8, g+12 of column j), chunk (q, u) of window tile q:
+//   A1 chunk lane l: A1[l%16][16q + 4u + l/16]     stored at position 4h+u
 //   -V chunk lane l: -Vt[16q + l%16][4u + l/16]    stored at position
-//                                                  4NT + u*NT + (NT-1-q)
-// i.e. in exactly the order the main kernel consumes them.
+//                    4NT + u*NT + (NT-1-h) (real), 4NT + 4(NT-1-h) + u (complex)
+// where h = (q + rot) mod NT is the register tile that holds window tile q
+// during this block: the main kernel never moves a tile between registers,
+// the window's top tile sits in register tile rot = (-o) mod NT in the o-th
+// block of a slot.  So the chunks are stored in exactly the order the main
+// kernel consumes them.
 // --------------------------------------------------------------------------
 // Shared-memory image of one block's compact-WY factor (see above).
 template <int NB, bool CPLX>
@@ -324,10 +328,14 @@ __device__ inline void pack_block(int64_t n, const double* __restrict__ hv,
     const auto& Vt = W.Vt;
     const auto& Tm = W.Tm;
     const int tid = threadIdx.x;
+    // register tile of window tile 0 in this block (the block's position in
+    // its slot's sequence is W.t - W.j * NB/16)
+    const int rot = (int)((NT - (W.t - W.j * (NB / 16)) % NT) % NT);
     // A1 chunks and -V chunks
     double* out = ws + (size_t)blk * G::PB;
     for (int idx = tid; idx < NT * 4 * 64; idx += 256) {
         const int lane = idx % 64, qu = idx / 64, q = qu / 4, u = qu % 4;
+        const int h = (q + rot) % NT;
         {   // A1[p][r] = sum_{q' >= p} T[p][q'] conj(Vt[r][q'])
             const int p = lane % 16, r = 16 * q + 4 * u + lane / 16;
             double ar = 0.0, ai = 0.0;
@@ -341,15 +349,15 @@ __device__ inline void pack_block(int64_t n, const double* __restrict__ hv,
                     ar += tr * vr;
                 }
             }
-            out[qu * G::CHUNK + lane] = ar;
-            if (CPLX) out[qu * G::CHUNK + 64 + lane] = ai;
+            out[(4 * h + u) * G::CHUNK + lane] = ar;
+            if (CPLX) out[(4 * h + u) * G::CHUNK + 64 + lane] = ai;
         }
         {   // -V chunks in the order the main kernel reads them.  Real: u
             // ascending, and within each u the tiles from the bottom of the
             // window up.  Complex: tile by tile from the bottom up, u
             // ascending inside a tile.
             const int r = 16 * q + lane % 16, p = 4 * u + lane / 16;
-            const int pos = CPLX ? (NT - 1 - q) * 4 + u : u * NT + (NT - 1 - q);
+            const int pos = CPLX ? (NT - 1 - h) * 4 + u : u * NT + (NT - 1 - h);
             out[G::A1_DBL + pos * G::CHUNK + lane] = -Vt[r][p][0];
             if (CPLX) out[G::A1_DBL + pos * G::CHUNK + 64 + lane] = -Vt[r][p][NC - 1];
         }
@@ -579,18 +587,23 @@ __device__ inline void lds_get(Tile<CPLX> (&t)[CT], const double* __restrict__ s
 }
 
 // Main blocked kernel.  Per block the operand stream is consumed in order:
-//   chunks 0 .. 4NT-1       A1 chunk (q, u) = (c/4, c%4):   Y += A1 * Zwin
-//   chunks 4NT .. 8NT-1     -V chunk (u, q), u ascending, q descending:
-//                           Zwin += (-V) * Y
-// During the last u pass (u = 3) each tile's final MFMA writes its result
-// one tile lower in the register window, so the slide of the window by one
-// tile costs no data movement; the bottom tile leaves as `zret`.
+//   chunks 0 .. 4NT-1       A1 chunk (h, u) = (c/4, c%4):   Y += A1 * Zwin
+//   chunks 4NT .. 8NT-1     -V chunks:                       Zwin += (-V) * Y
+//                           real: (u, h), u ascending, h descending;
+//                           complex: (h, u), h descending, u ascending
+// where h is a register tile.  Window tiles never move between registers
+// (a loop-carried rotation would cost a register copy of the whole window per
+// block): in the o-th block of a slot, window tile q (q = 0 at the top) lives
+// in register tile (q + rot) mod NT with rot = (-o) mod NT, and the pack
+// kernel stores every block's chunks in that order.  When the window slides,
+// the bottom tile (register tile rot - 1) retires and its registers take the
+// next block's top tile.
 //
 // blocked_strip runs the whole back-transformation of column strip `strip`
 // (columns 16*CT*strip ..) with the NW waves of the calling workgroup; wsb
-// is the problem's packed-block array, prog the workgroup's LDS progress
-// array, all zero on entry.  On the (never expected) time-out of a progress
-// wait a wave sets *err and leaves.
+// is the problem's packed-block array, S the workgroup's LDS state, all zero
+// on entry.  On the (never expected) time-out of a progress wait a wave sets
+// *err and leaves.
 //
 // With CKPT (the first pass of the adjoint), every block's input window is
 // also written to ckpt, one 16x16 tile at a time in register order:
@@ -636,6 +649,7 @@ __device__ inline void blocked_strip(int64_t n, int64_t nev, const double* __res
         const int need0 = (int)((j - 1) * (nblk + 1));   // + t + 1: slot j-1 done block t
         if (j > 0 && !wait_progress(prog, wprev, need0 + (int)t0 + 1, err, lane)) return;
         int64_t p0 = n - 3 - KB * t0 - 15 + j * NB;
+        // first block of the slot: window tile q in register tile q
 #pragma unroll
         for (int q = 0; q < NT; ++q) {
             const bool inside = cols_inside && p0 + 16 * q >= 0 && p0 + 16 * q + 16 <= n;
@@ -647,16 +661,20 @@ __device__ inline void blocked_strip(int64_t n, int64_t nev, const double* __res
 #pragma unroll
         for (int c = 0; c < D; ++c) load_chunk<CPLX, D>(ops, 0, c, lane, ring_re, ring_im, c);
 
+        int rot = 0;   // register tile of the window's top tile (wave-uniform)
         for (int64_t t = t0; t < nblk; ++t, boff += G::PB * sizeof(double), p0 -= KB) {
             const bool has_next = t + 1 < nblk;
+            const int ret = rot == 0 ? NT - 1 : rot - 1;   // register tile of the bottom tile
             if constexpr (CKPT) {
                 double* cp = ckpt + ((size_t)(slot_base(j, nblk, nt1) + t - t0) * NT * nstrips +
                                      strip) * 256 + lane;
 #pragma unroll
-                for (int q = 0; q < NT; ++q)
+                for (int h = 0; h < NT; ++h) {
+                    const int q = h >= rot ? h - rot : h + NT - rot;
 #pragma unroll
                     for (int e = 0; e < 4; ++e)
-                        cp[(size_t)q * nstrips * 256 + e * 64] = zt[q][0].re[e];
+                        cp[(size_t)q * nstrips * 256 + e * 64] = zt[h][0].re[e];
+                }
             }
             // the top tile of the next block: slot j-1 must have retired it.
             // From wave w-1's exchange ring when it put it there (slot j-1 is
@@ -677,7 +695,6 @@ __device__ inline void blocked_strip(int64_t n, int64_t nev, const double* __res
                                     inside);
             }
 
-            Tile<CPLX> zsh[NT + 1][CT];   // window after the slide; zsh[NT] retires
             // operand chunk c of this block sits in ring slot c % D; as soon
             // as it has been read the slot is refilled with chunk c + D
             // (running into the next block).  (Refilling only after the
@@ -692,7 +709,7 @@ __device__ inline void blocked_strip(int64_t n, int64_t nev, const double* __res
                                         ring_re, ring_im, slot);
             };
             bool xfail = false;
-            auto store_bottom = [&]() {   // the retiring tile, once it is final
+            auto store_bottom = [&](const Tile<CPLX> (&zb)[CT]) {   // the final bottom tile
                 if (!has_next) return;
                 // to wave w+1 through LDS: slot j+1 exists, is in this round, and
                 // this is not one of the first NT tiles (its initial window)
@@ -702,7 +719,7 @@ __device__ inline void blocked_strip(int64_t n, int64_t nev, const double* __res
                         xfail = true;
                         return;
                     }
-                    lds_put<CPLX, CT>(&S.ring[w][xput % XR][0], zsh[NT], lane);
+                    lds_put<CPLX, CT>(&S.ring[w][xput % XR][0], zb, lane);
                     ++xput;
                     __hip_atomic_store(&S.written[w], xput, __ATOMIC_RELEASE,
                                        __HIP_MEMORY_SCOPE_WORKGROUP);
@@ -711,15 +728,15 @@ __device__ inline void blocked_strip(int64_t n, int64_t nev, const double* __res
                     const bool inside = cols_inside && rb >= 0 && rb + 16 <= n;
 #pragma unroll
                     for (int cc = 0; cc < CT; ++cc)
-                        store_tile<CPLX>(zsh[NT][cc], Z, ldz, n, nev, rb + rsub,
-                                         col_base + 16 * cc, inside);
+                        store_tile<CPLX>(zb[cc], Z, ldz, n, nev, rb + rsub, col_base + 16 * cc,
+                                         inside);
                 }
             };
 
             if constexpr (CPLX) {
-                // Complex products with three real MFMAs each (Gauss):
-                //   (a + ib)(x + iy) = (ax - by) + i((a + b)(x + y) - ax - by)
-                // GEMM1: Y = A1 * Zwin, accumulating ax, by and (a+b)(x+y).
+                // Complex products with three real MFMAs each.
+                // GEMM1 (Gauss): Y = A1 * Zwin from P1 = sum ax, P2 = sum by and
+                // P3 = sum (a+b)(x+y), (a + ib)(x + iy) = (P1 - P2) + i(P3 - P1 - P2).
                 d4 ya[CT], yb[CT], yc[CT];
 #pragma unroll
                 for (int cc = 0; cc < CT; ++cc) ya[cc] = yb[cc] = yc[cc] = d4{0.0, 0.0, 0.0, 0.0};
@@ -728,114 +745,106 @@ __device__ inline void blocked_strip(int64_t n, int64_t nev, const double* __res
                     const double ar = ring_re[c % D], ai = ring_im[c % D];
                     refill(c);
                     const double as = ar + ai;
-                    const int q = c / 4, u = c % 4;
+                    const int h = c / 4, u = c % 4;
 #pragma unroll
                     for (int cc = 0; cc < CT; ++cc) {
-                        const double zr = zt[q][cc].re[u], zi = zt[q][cc].im[u];
+                        const double zr = zt[h][cc].re[u], zi = zt[h][cc].im[u];
                         ya[cc] = mfma_n<0>(ar, zr, ya[cc]);
                         yb[cc] = mfma_n<0>(ai, zi, yb[cc]);
                         yc[cc] = mfma_n<0>(as, zr + zi, yc[cc]);
                     }
                 }
-                Tile<true> y[CT];
-                double ys[CT][4];
+                // GEMM2 in the other three-product form, which accumulates in
+                // place: with -V = a + ib and Y = c + id,
+                //   Re += (a+b)c - b(c+d),   Im += (a+b)c + a(d-c),
+                // the B operands c = P1 - P2, -(c+d) = 2 P2 - P3, d-c = P3 - 2 P1.
+                d4 yr[CT], ym[CT], yk[CT], kk[CT];
 #pragma unroll
-                for (int cc = 0; cc < CT; ++cc) {
-                    y[cc].re = ya[cc] - yb[cc];
-                    y[cc].im = yc[cc] - ya[cc] - yb[cc];
+                for (int cc = 0; cc < CT; ++cc)
 #pragma unroll
-                    for (int u = 0; u < 4; ++u) ys[cc][u] = y[cc].re[u] + y[cc].im[u];
-                }
-                // GEMM2: Zwin += (-V) * Y, tile by tile from the bottom of the
-                // window up (the retiring tile first); the result of tile q
-                // lands in zsh[q+1], which slides the window by one tile.
+                    for (int e = 0; e < 4; ++e) {
+                        yr[cc][e] = ya[cc][e] - yb[cc][e];
+                        ym[cc][e] = __builtin_fma(2.0, yb[cc][e], -yc[cc][e]);
+                        yk[cc][e] = __builtin_fma(-2.0, ya[cc][e], yc[cc][e]);
+                    }
+                // tile by tile (register tiles from NT-1 down), u ascending
 #pragma unroll
                 for (int c2 = 0; c2 < 4 * NT; ++c2) {
                     const int c = 4 * NT + c2;
                     const double ar = ring_re[c % D], ai = ring_im[c % D];
                     refill(c);
                     const double as = ar + ai;
-                    const int q = NT - 1 - c2 / 4, u = c2 % 4;
+                    const int h = NT - 1 - c2 / 4, u = c2 % 4;
 #pragma unroll
                     for (int cc = 0; cc < CT; ++cc) {
-                        // per tile: sum of ax in dst.re, sum of by in zt.im (free
-                        // after its use as a B operand in GEMM1), and
-                        // Z.im + sum of (a+b)(x+y) directly in dst.im
-                        Tile<true>& dst = zsh[q + 1][cc];
-                        if (u == 0) {
-                            dst.re = mfma_n<0>(ar, y[cc].re[0], d4{0.0, 0.0, 0.0, 0.0});
-                            dst.im = mfma_n<0>(as, ys[cc][0], zt[q][cc].im);
-                            zt[q][cc].im = mfma_n<0>(ai, y[cc].im[0], d4{0.0, 0.0, 0.0, 0.0});
-                        } else {
-                            dst.re = mfma_n<0>(ar, y[cc].re[u], dst.re);
-                            dst.im = mfma_n<0>(as, ys[cc][u], dst.im);
-                            zt[q][cc].im = mfma_n<0>(ai, y[cc].im[u], zt[q][cc].im);
-                        }
+                        zt[h][cc].re = mfma_n<0>(ai, ym[cc][u], zt[h][cc].re);
+                        zt[h][cc].im = mfma_n<0>(ar, yk[cc][u], zt[h][cc].im);
+                        kk[cc] = mfma_n<0>(as, yr[cc][u], u == 0 ? d4{0.0, 0.0, 0.0, 0.0} : kk[cc]);
                         if (u == 3) {
-                            const d4 ta = dst.re, tb = zt[q][cc].im;
-                            dst.re = zt[q][cc].re + (ta - tb);
-                            dst.im = dst.im - (ta + tb);
+                            zt[h][cc].re += kk[cc];
+                            zt[h][cc].im += kk[cc];
                         }
                     }
-                    if (u == 3 && q == NT - 1) store_bottom();
                 }
             } else {
                 Tile<CPLX> y[2][CT];   // two partial sums: more independent MFMA chains
 #pragma unroll
-                for (int h = 0; h < 2; ++h)
+                for (int hp = 0; hp < 2; ++hp)
 #pragma unroll
-                    for (int c = 0; c < CT; ++c) y[h][c].re = d4{0.0, 0.0, 0.0, 0.0};
+                    for (int c = 0; c < CT; ++c) y[hp][c].re = d4{0.0, 0.0, 0.0, 0.0};
 #pragma unroll
                 for (int c = 0; c < NCH; ++c) {
                     const double ar = ring_re[c % D];
                     refill(c);
                     if (c < 4 * NT) {
                         // Y += A1(:, chunk) * Zwin(chunk, :)
-                        const int q = c / 4, u = c % 4, h = q & 1;
+                        const int h = c / 4, u = c % 4, hp = h & 1;
 #pragma unroll
                         for (int cc = 0; cc < CT; ++cc)
-                            y[h][cc].re = mfma_n<0>(ar, zt[q][cc].re[u], y[h][cc].re);
+                            y[hp][cc].re = mfma_n<0>(ar, zt[h][cc].re[u], y[hp][cc].re);
                         if (c == 4 * NT - 1) {
 #pragma unroll
                             for (int cc = 0; cc < CT; ++cc) y[0][cc].re += y[1][cc].re;
                         }
                     } else {
-                        // Zwin(tile q, :) += (-V)(tile q, chunk u) * Y(chunk u, :)
-                        const int c2 = c - 4 * NT, u = c2 / NT, q = NT - 1 - c2 % NT;
+                        // Zwin(tile h, :) += (-V)(tile h, chunk u) * Y(chunk u, :)
+                        const int c2 = c - 4 * NT, u = c2 / NT, h = NT - 1 - c2 % NT;
 #pragma unroll
-                        for (int cc = 0; cc < CT; ++cc) {
-                            const Tile<CPLX>& src = zt[q][cc];
-                            Tile<CPLX>& dst = (u == 3) ? zsh[q + 1][cc] : zt[q][cc];
-                            dst.re = mfma_n<0>(ar, y[0][cc].re[u], src.re);
-                        }
-                        if (u == 3 && q == NT - 1) store_bottom();
+                        for (int cc = 0; cc < CT; ++cc)
+                            zt[h][cc].re = mfma_n<0>(ar, y[0][cc].re[u], zt[h][cc].re);
                     }
                 }
             }
 
+            // the bottom tile is final: hand it off; its registers take the
+            // next block's top tile
+#pragma unroll
+            for (int h = 0; h < NT; ++h)
+                if (h == ret) {
+                    store_bottom(zt[h]);
+                    if (has_next) {
+#pragma unroll
+                        for (int c = 0; c < CT; ++c) zt[h][c] = znext[c];
+                    }
+                }
             if (xfail) return;
             if (!has_next) {
                 // the slot's last block: the whole window is final
 #pragma unroll
-                for (int q = 0; q < NT; ++q)
+                for (int h = 0; h < NT; ++h) {
+                    const int q = h >= rot ? h - rot : h + NT - rot;
 #pragma unroll
                     for (int c = 0; c < CT; ++c)
-                        store_tile<CPLX>(zsh[q + 1][c], Z, ldz, n, nev, p0 + 16 * q + rsub,
+                        store_tile<CPLX>(zt[h][c], Z, ldz, n, nev, p0 + 16 * q + rsub,
                                          col_base + 16 * c);
+                }
             }
             if (xin)   // the exchange tile read at the start of this block is in registers
                 __hip_atomic_store(&S.consumed[w - 1], xget, __ATOMIC_RELEASE,
                                    __HIP_MEMORY_SCOPE_WORKGROUP);
             __hip_atomic_store(&prog[w], (int)(j * (nblk + 1) + t + 1), __ATOMIC_RELEASE,
                                __HIP_MEMORY_SCOPE_WORKGROUP);
-            if (has_next) {
-#pragma unroll
-                for (int q = 1; q < NT; ++q)
-#pragma unroll
-                    for (int c = 0; c < CT; ++c) zt[q][c] = zsh[q][c];
-#pragma unroll
-                for (int c = 0; c < CT; ++c) zt[0][c] = znext[c];
-            }
+            rot = ret;
         }
     }
 }
