@@ -494,6 +494,28 @@ __device__ inline bool wait_progress(int* prog, int idx, int need, unsigned* err
     return true;
 }
 
+// The same wait for a counter that only grows, with `seen` the last value
+// this wave read from it: when that already satisfies the wait, the LDS
+// round trip is skipped (the acquire that read `seen` also made visible
+// everything released before any smaller value).
+__device__ inline bool wait_counter(int* ctr, int idx, int need, unsigned* err, int lane,
+                                    int& seen)
+{
+    if (seen >= need) return true;
+    unsigned spins = 0;
+    int v;
+    while ((v = __hip_atomic_load(&ctr[idx], __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_WORKGROUP)) <
+           need) {
+        __builtin_amdgcn_s_sleep(2);
+        if (++spins > (1u << 26)) {
+            if (lane == 0) atomicOr(err, 1u);
+            return false;
+        }
+    }
+    seen = v;
+    return true;
+}
+
 // Operand ring depth (chunks loaded ahead of use).  The ring position of a
 // chunk is its index in the block's stream modulo D, and the ring runs on
 // into the next block, so D must divide the chunk count per block.  Real
@@ -619,6 +641,8 @@ __device__ inline void blocked_strip(int64_t n, int64_t nev, const double* __res
     constexpr int XR = StripLds<NB, CT, CPLX, NW>::R;
     int* prog = S.prog;
     int xput = 0, xget = 0;   // exchange tiles this wave has put / taken so far
+    // last values read from the counters this wave waits on (all only grow)
+    int seen_prog = 0, seen_written = 0, seen_consumed = 0;
     static_assert(!CKPT || (CT == 1 && !CPLX), "checkpoints: real, one 16-column tile");
     using G = Geo<NB, CPLX>;
     constexpr int NT = G::NT;
@@ -647,7 +671,8 @@ __device__ inline void blocked_strip(int64_t n, int64_t nev, const double* __res
                         (uint32_t)((nblk - t0) * G::PB * sizeof(double)));
         uint32_t boff = 0;
         const int need0 = (int)((j - 1) * (nblk + 1));   // + t + 1: slot j-1 done block t
-        if (j > 0 && !wait_progress(prog, wprev, need0 + (int)t0 + 1, err, lane)) return;
+        if (j > 0 && !wait_counter(prog, wprev, need0 + (int)t0 + 1, err, lane, seen_prog))
+            return;
         int64_t p0 = n - 3 - KB * t0 - 15 + j * NB;
         // first block of the slot: window tile q in register tile q
 #pragma unroll
@@ -683,11 +708,13 @@ __device__ inline void blocked_strip(int64_t n, int64_t nev, const double* __res
             Tile<CPLX> znext[CT];
             const bool xin = has_next && w > 0 && t + 2 < nblk;
             if (xin) {
-                if (!wait_progress(S.written, w - 1, xget + 1, err, lane)) return;
+                if (!wait_counter(S.written, w - 1, xget + 1, err, lane, seen_written)) return;
                 lds_get<CPLX, CT>(znext, &S.ring[w - 1][xget % XR][0], lane);
                 ++xget;
             } else if (has_next) {
-                if (j > 0 && !wait_progress(prog, wprev, need0 + (int)t + 2, err, lane)) return;
+                if (j > 0 &&
+                    !wait_counter(prog, wprev, need0 + (int)t + 2, err, lane, seen_prog))
+                    return;
                 const bool inside = cols_inside && p0 - 16 >= 0 && p0 <= n;
 #pragma unroll
                 for (int c = 0; c < CT; ++c)
@@ -715,7 +742,7 @@ __device__ inline void blocked_strip(int64_t n, int64_t nev, const double* __res
                 // this is not one of the first NT tiles (its initial window)
                 const bool xout = w < NW - 1 && j + 1 < J && t >= t0 + NT;
                 if (xout) {
-                    if (!wait_progress(S.consumed, w, xput - XR + 1, err, lane)) {
+                    if (!wait_counter(S.consumed, w, xput - XR + 1, err, lane, seen_consumed)) {
                         xfail = true;
                         return;
                     }
