@@ -118,8 +118,15 @@ __global__ __launch_bounds__(64 * NW) void k_blocked_ckpt(int64_t n, int64_t nev
         n, nev, blocks, Z, ldz, err, blockIdx.x, S, ckpt, gridDim.x);
 }
 
-// Order the LDS writes of this wave before its following LDS reads.
-__device__ inline void lds_order() { asm volatile("s_waitcnt lgkmcnt(0)" ::: "memory"); }
+// Lane-to-lane exchange through LDS inside one wave: the wave's LDS
+// operations complete in order, so only the compiler must keep the writes
+// before the reads (wavefront-scope fences emit no wait instruction).
+__device__ inline void wave_lds_sync()
+{
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
 
 // Backward pass.  Workgroup = one 16-column strip, NW waves = NW slots in
 // flight.  Slot j runs its blocks t = nblk-1 down to j*nbw/16; block (t, j)
@@ -172,15 +179,27 @@ __global__ __launch_bounds__(64 * NW) void k_adj_blocked(int64_t n, int64_t nev,
             const bool inside = cols_inside && p0 + 16 * q >= 0 && p0 + 16 * q + 16 <= n;
             load_tile<false>(g[q], G, ldg, n, nev, p0 + 16 * q + rsub, col, inside);
         }
-
-        for (int64_t t = nblk - 1; t >= t0; --t, p0 += KB) {
-            const int64_t b = slot_base(j, nblk, nt1) + (t - t0);
-            const double* __restrict__ pk = apk + (size_t)b * A::APB;
+        // checkpoint of the slot's first block; later blocks' checkpoints are
+        // fetched during the previous block (see the P1/P2 loop)
+        {
+            const int64_t b = slot_base(j, nblk, nt1) + (nblk - 1 - t0);
             const double* __restrict__ cp = ckpt + ((size_t)b * NT * nstrips + strip) * 256 + lane;
 #pragma unroll
             for (int q = 0; q < NT; ++q)
 #pragma unroll
-                for (int e = 0; e < 4; ++e) x[q].re[e] = cp[(size_t)q * nstrips * 256 + e * 64];
+                for (int e = 0; e < 4; ++e)
+                    x[q].re[e] = __builtin_nontemporal_load(&cp[(size_t)q * nstrips * 256 + e * 64]);
+        }
+
+        for (int64_t t = nblk - 1; t >= t0; --t, p0 += KB) {
+            const int64_t b = slot_base(j, nblk, nt1) + (t - t0);
+            const double* __restrict__ pk = apk + (size_t)b * A::APB;
+            // the -V chunks of Gi are read now, ahead of this block's partial
+            // stores: loads issued after stores wait for them (one in-order
+            // vector-memory counter)
+            double nv[4 * NT];
+#pragma unroll
+            for (int c = 0; c < 4 * NT; ++c) nv[c] = pk[A::NV_OFF + c * 64 + lane];
 
             // Bt = V^T Go, Ax = V^T X
             d4 bt[2], ax[2];
@@ -202,18 +221,6 @@ __global__ __launch_bounds__(64 * NW) void k_adj_blocked(int64_t n, int64_t nev,
                 Y = mfma(pk[A::TT_OFF + u * 64 + lane], Bt[u], Y);
             }
             double* __restrict__ pp = part + ((size_t)b * nstrips + strip) * A::PPB;
-            {   // dtau_p partial: -sum over the strip's columns of g_p w_p
-                double pr[4];
-#pragma unroll
-                for (int e = 0; e < 4; ++e) pr[e] = -Wt[e] * Gt[e];
-#pragma unroll
-                for (int off = 1; off < 16; off <<= 1)
-#pragma unroll
-                    for (int e = 0; e < 4; ++e) pr[e] += __shfl_xor(pr[e], off);
-                if (cl == 0)
-#pragma unroll
-                    for (int e = 0; e < 4; ++e) pp[A::DT_OFF + rsub + 4 * e] = pr[e];
-            }
             // P1 = Go W and P2 = X g: contractions over the strip's columns,
             // fed to the MFMA through per-wave LDS transposes
 #pragma unroll
@@ -221,13 +228,31 @@ __global__ __launch_bounds__(64 * NW) void k_adj_blocked(int64_t n, int64_t nev,
                 Mw[rsub + 4 * e][cl] = Wt[e];
                 Mg[rsub + 4 * e][cl] = Gt[e];
             }
-            lds_order();
-            double bw[4], bg[4];
+            wave_lds_sync();
+            double bw[4], bg[4];   // chunk u of W^T and g^T: B operands
 #pragma unroll
             for (int u = 0; u < 4; ++u) {
                 bw[u] = Mw[cl][4 * u + rsub];
                 bg[u] = Mg[cl][4 * u + rsub];
             }
+            {   // dtau_p partial = -sum over the strip's columns of g_p w_p,
+                // the diagonal of g W^T (bg read as the A operand is chunk u
+                // of g, reflectors x columns); element (p, p) sits in lane
+                // p + 16 (p % 4), element p / 4
+                d4 gw = d4{0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+                for (int u = 0; u < 4; ++u) gw = mfma(bg[u], bw[u], gw);
+                const int e = (cl - rsub) >> 2;
+                if (((cl - rsub) & 3) == 0 && cl >= rsub)
+                    pp[A::DT_OFF + cl] = -(e == 0 ? gw[0] : e == 1 ? gw[1] : e == 2 ? gw[2] : gw[3]);
+            }
+            // the next block's checkpoint goes into x tile by tile once the
+            // tile's last use (its transpose below) is done, before the stores.
+            // Checkpoints and partials each cross memory once: non-temporal
+            // accesses keep them from evicting the operands from the caches.
+            const bool xnext = t > t0;
+            const double* __restrict__ cpn =
+                ckpt + ((size_t)(b - 1) * NT * nstrips + strip) * 256 + lane;
 #pragma unroll
             for (int q = 0; q < NT; ++q) {
 #pragma unroll
@@ -235,14 +260,18 @@ __global__ __launch_bounds__(64 * NW) void k_adj_blocked(int64_t n, int64_t nev,
                     Ta[rsub + 4 * e][cl] = g[q].re[e];
                     Tb[rsub + 4 * e][cl] = x[q].re[e];
                 }
-                lds_order();
+                wave_lds_sync();
+                if (xnext)
+#pragma unroll
+                    for (int e = 0; e < 4; ++e)
+                        x[q].re[e] = __builtin_nontemporal_load(&cpn[(size_t)q * nstrips * 256 + e * 64]);
                 double ag[4], axx[4];
 #pragma unroll
                 for (int u = 0; u < 4; ++u) {
                     ag[u] = Ta[cl][4 * u + rsub];
                     axx[u] = Tb[cl][4 * u + rsub];
                 }
-                lds_order();
+                wave_lds_sync();   // the next tile's writes stay behind these reads
                 d4 p1 = d4{0.0, 0.0, 0.0, 0.0}, p2 = p1;
 #pragma unroll
                 for (int u = 0; u < 4; ++u) {
@@ -251,15 +280,15 @@ __global__ __launch_bounds__(64 * NW) void k_adj_blocked(int64_t n, int64_t nev,
                 }
 #pragma unroll
                 for (int e = 0; e < 4; ++e) {
-                    pp[q * 256 + e * 64 + lane] = p1[e];
-                    pp[A::P2_OFF + q * 256 + e * 64 + lane] = p2[e];
+                    __builtin_nontemporal_store(p1[e], &pp[q * 256 + e * 64 + lane]);
+                    __builtin_nontemporal_store(p2[e], &pp[A::P2_OFF + q * 256 + e * 64 + lane]);
                 }
             }
             // Gi = Go - V Y
 #pragma unroll
             for (int c = 0; c < 4 * NT; ++c) {
                 const int q = c >> 2, u = c & 3;
-                g[q].re = mfma(pk[A::NV_OFF + c * 64 + lane], Y[u], g[q].re);
+                g[q].re = mfma(nv[c], Y[u], g[q].re);
             }
             // slide down: the top tile leaves for slot j-1, a new bottom tile
             // arrives from slot j+1 (or from G when slot j+1 has no block)
@@ -328,8 +357,10 @@ __global__ __launch_bounds__(256) void k_adj_finish(int64_t n, int64_t nstrips,
         int64_t s = 0;
         for (; s + 8 <= nstrips; s += 8)
 #pragma unroll
-            for (int k = 0; k < 8; ++k) a8[k] += pb[(size_t)(s + k) * A::PPB + idx];
-        for (int k = 0; s < nstrips; ++s, ++k) a8[k] += pb[(size_t)s * A::PPB + idx];
+            for (int k = 0; k < 8; ++k)
+                a8[k] += __builtin_nontemporal_load(&pb[(size_t)(s + k) * A::PPB + idx]);
+        for (int k = 0; s < nstrips; ++s, ++k)
+            a8[k] += __builtin_nontemporal_load(&pb[(size_t)s * A::PPB + idx]);
         const double acc = ((a8[0] + a8[1]) + (a8[2] + a8[3])) + ((a8[4] + a8[5]) + (a8[6] + a8[7]));
         if (idx < A::DT_OFF) {
             const int which = idx / A::P2_OFF, rem = idx % A::P2_OFF;

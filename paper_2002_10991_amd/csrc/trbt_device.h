@@ -628,7 +628,9 @@ __device__ inline void lds_get(Tile<CPLX> (&t)[CT], const double* __restrict__ s
 // *err and leaves.
 //
 // With CKPT (the first pass of the adjoint), every block's input window is
-// also written to ckpt, one 16x16 tile at a time in register order:
+// also written to ckpt (non-temporal stores: read once, much later, so they
+// should not displace the operand stream in the caches), one 16x16 tile at a
+// time in register order:
 //   ckpt[(((b * NT + q) * nstrips + strip) * 4 + e) * 64 + lane]
 // b = the block's slot-major index, q = tile of the window, e = element.
 template <int NB, int CT, bool CPLX, int D, int NW, bool CKPT = false>
@@ -698,7 +700,8 @@ __device__ inline void blocked_strip(int64_t n, int64_t nev, const double* __res
                     const int q = h >= rot ? h - rot : h + NT - rot;
 #pragma unroll
                     for (int e = 0; e < 4; ++e)
-                        cp[(size_t)q * nstrips * 256 + e * 64] = zt[h][0].re[e];
+                        __builtin_nontemporal_store(zt[h][0].re[e],
+                                                    &cp[(size_t)q * nstrips * 256 + e * 64]);
                 }
             }
             // the top tile of the next block: slot j-1 must have retired it.
