@@ -21,11 +21,14 @@
 //   P1 = Go W, P2 = X g  (sums over columns),  dtau_p = -sum_c g_p w_p,
 // M = V^T V.  The intermediate states inside a block are never formed: the
 // block's input window is the checkpoint (one per slot every 16 stages),
-// written by a first forward pass.  The backward pass walks every slot's
+// written by a first forward pass.  The backward sweep walks every slot's
 // blocks from the lowest stages up (the window slides down one tile per
-// block) in a wave pipeline that mirrors the forward one; the column sums
-// P1, P2, dtau are written per column strip and reduced in a fixed order by
-// a finishing kernel, so results are deterministic.
+// block) in a wave pipeline that mirrors the forward one, propagating only
+// the gradient (Gi) and saving each block's Go like a checkpoint.  A
+// reduction pass then takes one block per workgroup: it forms w, g and the
+// column sums P1, P2, dtau over all column strips in registers (fixed order,
+// so results are deterministic) and applies the corrections.  No per-strip
+// partial sums cross memory.
 //
 // Streaming path (any nbw): one lane per column; the column's state is
 // checkpointed at the start of every 16-stage block, each block is
@@ -56,9 +59,6 @@ struct AdjGeo {
     static constexpr int T_OFF = TT_OFF + 256;           // T, row major 16 x 16
     static constexpr int TAU_OFF = T_OFF + 256;          // tau_p
     static constexpr int APB = (TAU_OFF + 16 + 31) / 32 * 32;   // doubles per block
-    static constexpr int P2_OFF = NT * 256;              // partials: P1 tiles, P2 tiles,
-    static constexpr int DT_OFF = 2 * NT * 256;          //           dtau_p
-    static constexpr int PPB = DT_OFF + 32;              // doubles per (strip, block)
 };
 
 // Operand pack for the backward pass: one workgroup (256 threads) per block.
@@ -128,24 +128,24 @@ __device__ inline void wave_lds_sync()
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
-// Backward pass.  Workgroup = one 16-column strip, NW waves = NW slots in
+// Backward sweep.  Workgroup = one 16-column strip, NW waves = NW slots in
 // flight.  Slot j runs its blocks t = nblk-1 down to j*nbw/16; block (t, j)
 // needs (t+1, j) (same wave, earlier) and (t, j+1), whose retired top tile
 // is this block's new bottom tile.  Slot j is handled by wave
-// (J-1-j) mod NW, so slot j+1 is on the previous wave.
+// (J-1-j) mod NW, so slot j+1 is on the previous wave.  Per block the
+// gradient window Go becomes Gi = Q^T Go = Go - V (T^T (V^T Go)), and Go is
+// saved to gck in the checkpoint layout for the reduction pass.
 template <int NB, int NW>
-__global__ __launch_bounds__(64 * NW) void k_adj_blocked(int64_t n, int64_t nev,
-                                                         const double* __restrict__ apk,
-                                                         const double* __restrict__ ckpt,
-                                                         double* __restrict__ G, int64_t ldg,
-                                                         double* __restrict__ part,
-                                                         unsigned* __restrict__ err)
+__global__ __launch_bounds__(64 * NW) void k_adj_sweep(int64_t n, int64_t nev,
+                                                       const double* __restrict__ apk,
+                                                       double* __restrict__ G, int64_t ldg,
+                                                       double* __restrict__ gck,
+                                                       unsigned* __restrict__ err)
 {
     using A = AdjGeo<NB>;
     constexpr int NT = A::NT;
     constexpr int64_t nt1 = NB / 16;
     __shared__ int prog[NW];
-    __shared__ double lds[NW][4][16][17];
 
     const int lane = threadIdx.x & 63;
     const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
@@ -157,14 +157,11 @@ __global__ __launch_bounds__(64 * NW) void k_adj_blocked(int64_t n, int64_t nev,
     const int64_t J = sweeps_in_stage(n, NB, 0);
     const int64_t col = strip * 16 + (lane & 15);
     const bool cols_inside = (strip + 1) * 16 <= nev;
-    const int rsub = lane >> 4, cl = lane & 15;
+    const int rsub = lane >> 4;
     const int wprev = (w + NW - 1) % NW;
-    double (*Mw)[17] = lds[w][0];
-    double (*Mg)[17] = lds[w][1];
-    double (*Ta)[17] = lds[w][2];
-    double (*Tb)[17] = lds[w][3];
+    int seen = 0;   // last value read from prog[wprev]
 
-    Tile<false> g[NT], x[NT];
+    Tile<false> g[NT];
 
     for (int64_t j = J - 1 - w; j >= 0; j -= NW) {
         const int64_t t0 = j * nt1;
@@ -172,119 +169,46 @@ __global__ __launch_bounds__(64 * NW) void k_adj_blocked(int64_t n, int64_t nev,
         const int64_t t0s = (j + 1) * nt1;
         const int base = (int)((J - 1 - j) * (nblk + 1));    // + nblk - t after block t
         const int base_s = base - (int)(nblk + 1);           // the same for slot j+1
-        if (has_succ && !wait_progress(prog, wprev, base_s + 1, err, lane)) return;
+        if (has_succ && !wait_counter(prog, wprev, base_s + 1, err, lane, seen)) return;
         int64_t p0 = n - 3 - KB * (nblk - 1) - 15 + j * NB;
 #pragma unroll
         for (int q = 0; q < NT; ++q) {
             const bool inside = cols_inside && p0 + 16 * q >= 0 && p0 + 16 * q + 16 <= n;
             load_tile<false>(g[q], G, ldg, n, nev, p0 + 16 * q + rsub, col, inside);
         }
-        // checkpoint of the slot's first block; later blocks' checkpoints are
-        // fetched during the previous block (see the P1/P2 loop)
-        {
-            const int64_t b = slot_base(j, nblk, nt1) + (nblk - 1 - t0);
-            const double* __restrict__ cp = ckpt + ((size_t)b * NT * nstrips + strip) * 256 + lane;
-#pragma unroll
-            for (int q = 0; q < NT; ++q)
-#pragma unroll
-                for (int e = 0; e < 4; ++e)
-                    x[q].re[e] = __builtin_nontemporal_load(&cp[(size_t)q * nstrips * 256 + e * 64]);
-        }
 
         for (int64_t t = nblk - 1; t >= t0; --t, p0 += KB) {
             const int64_t b = slot_base(j, nblk, nt1) + (t - t0);
             const double* __restrict__ pk = apk + (size_t)b * A::APB;
-            // the -V chunks of Gi are read now, ahead of this block's partial
-            // stores: loads issued after stores wait for them (one in-order
-            // vector-memory counter)
-            double nv[4 * NT];
-#pragma unroll
-            for (int c = 0; c < 4 * NT; ++c) nv[c] = pk[A::NV_OFF + c * 64 + lane];
-
-            // Bt = V^T Go, Ax = V^T X
-            d4 bt[2], ax[2];
-            bt[0] = bt[1] = ax[0] = ax[1] = d4{0.0, 0.0, 0.0, 0.0};
+            // the block's operands are read ahead of its stores: loads issued
+            // after stores wait for them (one in-order vector-memory counter)
+            double vt[4 * NT], nv[4 * NT], tt[4];
 #pragma unroll
             for (int c = 0; c < 4 * NT; ++c) {
-                const int q = c >> 2, u = c & 3, h = q & 1;
-                const double a = pk[A::VT_OFF + c * 64 + lane];
-                bt[h] = mfma(a, g[q].re[u], bt[h]);
-                ax[h] = mfma(a, x[q].re[u], ax[h]);
+                vt[c] = pk[A::VT_OFF + c * 64 + lane];
+                nv[c] = pk[A::NV_OFF + c * 64 + lane];
             }
-            const d4 Bt = bt[0] + bt[1], Ax = ax[0] + ax[1];
-            // W^T = R^T Ax, g^T = S^T Bt, Y = T^T Bt
-            d4 Wt = d4{0.0, 0.0, 0.0, 0.0}, Gt = Wt, Y = Wt;
 #pragma unroll
-            for (int u = 0; u < 4; ++u) {
-                Wt = mfma(pk[A::RT_OFF + u * 64 + lane], Ax[u], Wt);
-                Gt = mfma(pk[A::ST_OFF + u * 64 + lane], Bt[u], Gt);
-                Y = mfma(pk[A::TT_OFF + u * 64 + lane], Bt[u], Y);
+            for (int u = 0; u < 4; ++u) tt[u] = pk[A::TT_OFF + u * 64 + lane];
+            // Go of this block, read once by the reduction pass: non-temporal
+            double* __restrict__ gp = gck + ((size_t)b * NT * nstrips + strip) * 256 + lane;
+#pragma unroll
+            for (int q = 0; q < NT; ++q)
+#pragma unroll
+                for (int e = 0; e < 4; ++e)
+                    __builtin_nontemporal_store(g[q].re[e], &gp[(size_t)q * nstrips * 256 + e * 64]);
+            // Bt = V^T Go, Y = T^T Bt, Gi = Go - V Y
+            d4 bt[2];
+            bt[0] = bt[1] = d4{0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+            for (int c = 0; c < 4 * NT; ++c) {
+                const int q = c >> 2, u = c & 3;
+                bt[q & 1] = mfma(vt[c], g[q].re[u], bt[q & 1]);
             }
-            double* __restrict__ pp = part + ((size_t)b * nstrips + strip) * A::PPB;
-            // P1 = Go W and P2 = X g: contractions over the strip's columns,
-            // fed to the MFMA through per-wave LDS transposes
+            const d4 Bt = bt[0] + bt[1];
+            d4 Y = d4{0.0, 0.0, 0.0, 0.0};
 #pragma unroll
-            for (int e = 0; e < 4; ++e) {
-                Mw[rsub + 4 * e][cl] = Wt[e];
-                Mg[rsub + 4 * e][cl] = Gt[e];
-            }
-            wave_lds_sync();
-            double bw[4], bg[4];   // chunk u of W^T and g^T: B operands
-#pragma unroll
-            for (int u = 0; u < 4; ++u) {
-                bw[u] = Mw[cl][4 * u + rsub];
-                bg[u] = Mg[cl][4 * u + rsub];
-            }
-            {   // dtau_p partial = -sum over the strip's columns of g_p w_p,
-                // the diagonal of g W^T (bg read as the A operand is chunk u
-                // of g, reflectors x columns); element (p, p) sits in lane
-                // p + 16 (p % 4), element p / 4
-                d4 gw = d4{0.0, 0.0, 0.0, 0.0};
-#pragma unroll
-                for (int u = 0; u < 4; ++u) gw = mfma(bg[u], bw[u], gw);
-                const int e = (cl - rsub) >> 2;
-                if (((cl - rsub) & 3) == 0 && cl >= rsub)
-                    pp[A::DT_OFF + cl] = -(e == 0 ? gw[0] : e == 1 ? gw[1] : e == 2 ? gw[2] : gw[3]);
-            }
-            // the next block's checkpoint goes into x tile by tile once the
-            // tile's last use (its transpose below) is done, before the stores.
-            // Checkpoints and partials each cross memory once: non-temporal
-            // accesses keep them from evicting the operands from the caches.
-            const bool xnext = t > t0;
-            const double* __restrict__ cpn =
-                ckpt + ((size_t)(b - 1) * NT * nstrips + strip) * 256 + lane;
-#pragma unroll
-            for (int q = 0; q < NT; ++q) {
-#pragma unroll
-                for (int e = 0; e < 4; ++e) {
-                    Ta[rsub + 4 * e][cl] = g[q].re[e];
-                    Tb[rsub + 4 * e][cl] = x[q].re[e];
-                }
-                wave_lds_sync();
-                if (xnext)
-#pragma unroll
-                    for (int e = 0; e < 4; ++e)
-                        x[q].re[e] = __builtin_nontemporal_load(&cpn[(size_t)q * nstrips * 256 + e * 64]);
-                double ag[4], axx[4];
-#pragma unroll
-                for (int u = 0; u < 4; ++u) {
-                    ag[u] = Ta[cl][4 * u + rsub];
-                    axx[u] = Tb[cl][4 * u + rsub];
-                }
-                wave_lds_sync();   // the next tile's writes stay behind these reads
-                d4 p1 = d4{0.0, 0.0, 0.0, 0.0}, p2 = p1;
-#pragma unroll
-                for (int u = 0; u < 4; ++u) {
-                    p1 = mfma(ag[u], bw[u], p1);
-                    p2 = mfma(axx[u], bg[u], p2);
-                }
-#pragma unroll
-                for (int e = 0; e < 4; ++e) {
-                    __builtin_nontemporal_store(p1[e], &pp[q * 256 + e * 64 + lane]);
-                    __builtin_nontemporal_store(p2[e], &pp[A::P2_OFF + q * 256 + e * 64 + lane]);
-                }
-            }
-            // Gi = Go - V Y
+            for (int u = 0; u < 4; ++u) Y = mfma(tt[u], Bt[u], Y);
 #pragma unroll
             for (int c = 0; c < 4 * NT; ++c) {
                 const int q = c >> 2, u = c & 3;
@@ -300,7 +224,7 @@ __global__ __launch_bounds__(64 * NW) void k_adj_blocked(int64_t n, int64_t nev,
 #pragma unroll
                 for (int q = 0; q + 1 < NT; ++q) g[q] = g[q + 1];
                 if (has_succ && t - 1 >= t0s &&
-                    !wait_progress(prog, wprev, base_s + (int)(nblk - (t - 1)), err, lane))
+                    !wait_counter(prog, wprev, base_s + (int)(nblk - (t - 1)), err, lane, seen))
                     return;
                 const int64_t r = p0 + KB + 16 * (NT - 1);
                 const bool inside = cols_inside && r >= 0 && r + 16 <= n;
@@ -316,25 +240,34 @@ __global__ __launch_bounds__(64 * NW) void k_adj_blocked(int64_t n, int64_t nev,
     }
 }
 
-// Finishing pass: one workgroup per block.  Sums the strips' partials in a
-// fixed order, applies the column-independent corrections and writes dv and
-// dtau of the block's reflectors.
-template <int NB>
-__global__ __launch_bounds__(256) void k_adj_finish(int64_t n, int64_t nstrips,
-                                                    const double* __restrict__ apk,
-                                                    const double* __restrict__ part,
-                                                    double* __restrict__ dv,
-                                                    double* __restrict__ dtau)
+// Reduction pass: one workgroup per block, RW waves.  From the block's input
+// window X (checkpoint) and output gradient Go of every column strip:
+//   w = R^T (V^T X), g = S^T (V^T Go), dtau_p = -sum_c g_p w_p,
+//   P1 = Go W, P2 = X g   (sums over all columns),
+// each wave summing its strips (s = w, w + RW, ...) in registers and the waves
+// then combined in wave order (the same result on every run); finally the
+// column-independent corrections give dv and dtau of the block's reflectors.
+template <int NB, int RW>
+__global__ __launch_bounds__(64 * RW) void k_adj_reduce(int64_t n, int64_t nstrips,
+                                                        const double* __restrict__ apk,
+                                                        const double* __restrict__ ckpt,
+                                                        const double* __restrict__ gck,
+                                                        double* __restrict__ dv,
+                                                        double* __restrict__ dtau)
 {
+    static_assert(RW * 64 == 256, "the finishing steps use 256 threads");
     using A = AdjGeo<NB>;
     constexpr int NT = A::NT, R = 16 * NT;
     constexpr int64_t nt1 = NB / 16;
+    __shared__ double tr[RW][2][16][17];   // per-wave transposes
     __shared__ double P1[R][17], P2[R][17], Vs[R][17];
     __shared__ double Ts[16][17], U1[16][17], U2[16][17], Cm[16][17];
     __shared__ double dts[16], taus[16];
     __shared__ int64_t s_j, s_t;
 
-    const int tid = threadIdx.x;
+    const int tid = threadIdx.x, lane = tid & 63;
+    const int w = __builtin_amdgcn_readfirstlane(tid >> 6);
+    const int rsub = lane >> 4, cl = lane & 15;
     const int64_t b = blockIdx.x;
     const int64_t nblk = (n - 2 + KB - 1) / KB;
     const int64_t J = sweeps_in_stage(n, NB, 0);
@@ -348,28 +281,107 @@ __global__ __launch_bounds__(256) void k_adj_finish(int64_t n, int64_t nstrips,
         s_t = lo * nt1 + (b - slot_base(lo, nblk, nt1));
     }
     const double* pk = apk + (size_t)b * A::APB;
-    // the block's partials from all strips are contiguous: [strip][PPB]
-    const double* __restrict__ pb = part + (size_t)b * nstrips * A::PPB;
-    for (int idx = tid; idx < A::DT_OFF + 16; idx += 256) {
-        // eight running sums (strip s into sum s % 8), combined in a fixed
-        // order: many loads in flight, the same result on every run
-        double a8[8] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
-        int64_t s = 0;
-        for (; s + 8 <= nstrips; s += 8)
+    double rt[4], st[4];
 #pragma unroll
-            for (int k = 0; k < 8; ++k)
-                a8[k] += __builtin_nontemporal_load(&pb[(size_t)(s + k) * A::PPB + idx]);
-        for (int k = 0; s < nstrips; ++s, ++k)
-            a8[k] += __builtin_nontemporal_load(&pb[(size_t)s * A::PPB + idx]);
-        const double acc = ((a8[0] + a8[1]) + (a8[2] + a8[3])) + ((a8[4] + a8[5]) + (a8[6] + a8[7]));
-        if (idx < A::DT_OFF) {
-            const int which = idx / A::P2_OFF, rem = idx % A::P2_OFF;
-            const int q = rem / 256, e = (rem % 256) / 64, l = rem % 64;
-            const int r = 16 * q + (l >> 4) + 4 * e, p = l & 15;
-            (which ? P2 : P1)[r][p] = acc;
-        } else {
-            dts[idx - A::DT_OFF] = acc;
+    for (int u = 0; u < 4; ++u) {
+        rt[u] = pk[A::RT_OFF + u * 64 + lane];
+        st[u] = pk[A::ST_OFF + u * 64 + lane];
+    }
+    double (*Ma)[17] = tr[w][0];
+    double (*Mb)[17] = tr[w][1];
+    d4 p1[NT], p2[NT], dg = d4{0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+    for (int q = 0; q < NT; ++q) p1[q] = p2[q] = d4{0.0, 0.0, 0.0, 0.0};
+
+    for (int64_t s = w; s < nstrips; s += RW) {
+        const size_t off = ((size_t)b * NT * nstrips + s) * 256 + lane;
+        Tile<false> x[NT], go[NT];
+#pragma unroll
+        for (int q = 0; q < NT; ++q)
+#pragma unroll
+            for (int e = 0; e < 4; ++e) {
+                x[q].re[e] = __builtin_nontemporal_load(&ckpt[off + (size_t)q * nstrips * 256 + e * 64]);
+                go[q].re[e] = __builtin_nontemporal_load(&gck[off + (size_t)q * nstrips * 256 + e * 64]);
+            }
+        // Ax = V^T X, Bt = V^T Go (V^T chunks from L1/L2: shared by the waves)
+        d4 ax[2], bt[2];
+        ax[0] = ax[1] = bt[0] = bt[1] = d4{0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+        for (int c = 0; c < 4 * NT; ++c) {
+            const int q = c >> 2, u = c & 3;
+            const double a = pk[A::VT_OFF + c * 64 + lane];
+            ax[q & 1] = mfma(a, x[q].re[u], ax[q & 1]);
+            bt[q & 1] = mfma(a, go[q].re[u], bt[q & 1]);
         }
+        const d4 Ax = ax[0] + ax[1], Bt = bt[0] + bt[1];
+        // W^T = R^T Ax, g^T = S^T Bt
+        d4 Wt = d4{0.0, 0.0, 0.0, 0.0}, Gt = Wt;
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            Wt = mfma(rt[u], Ax[u], Wt);
+            Gt = mfma(st[u], Bt[u], Gt);
+        }
+        // chunk u of W^T and g^T (B operands) through an LDS transpose
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+            Ma[rsub + 4 * e][cl] = Wt[e];
+            Mb[rsub + 4 * e][cl] = Gt[e];
+        }
+        wave_lds_sync();
+        double bw[4], bg[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            bw[u] = Ma[cl][4 * u + rsub];
+            bg[u] = Mb[cl][4 * u + rsub];
+        }
+        wave_lds_sync();
+        // g W^T: its diagonal is sum_c g_p w_p (bg read as the A operand is
+        // chunk u of g, reflectors x columns)
+#pragma unroll
+        for (int u = 0; u < 4; ++u) dg = mfma(bg[u], bw[u], dg);
+        // P1 += Go W, P2 += X g, tile by tile (Go and X transposed to A operands)
+#pragma unroll
+        for (int q = 0; q < NT; ++q) {
+#pragma unroll
+            for (int e = 0; e < 4; ++e) {
+                Ma[rsub + 4 * e][cl] = go[q].re[e];
+                Mb[rsub + 4 * e][cl] = x[q].re[e];
+            }
+            wave_lds_sync();
+            double ag[4], axx[4];
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                ag[u] = Ma[cl][4 * u + rsub];
+                axx[u] = Mb[cl][4 * u + rsub];
+            }
+            wave_lds_sync();
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                p1[q] = mfma(ag[u], bw[u], p1[q]);
+                p2[q] = mfma(axx[u], bg[u], p2[q]);
+            }
+        }
+    }
+    // combine the waves in order: P1[16q + rsub + 4e][cl] is element e of
+    // p1[q]; element (p, p) of g W^T sits in lane p + 16 (p % 4), element p / 4
+    const int de = (cl - rsub) >> 2;
+    const bool dlane = ((cl - rsub) & 3) == 0 && cl >= rsub;
+    for (int ww = 0; ww < RW; ++ww) {
+        if (w == ww) {
+#pragma unroll
+            for (int q = 0; q < NT; ++q)
+#pragma unroll
+                for (int e = 0; e < 4; ++e) {
+                    const int r = 16 * q + rsub + 4 * e;
+                    P1[r][cl] = (ww ? P1[r][cl] : 0.0) + p1[q][e];
+                    P2[r][cl] = (ww ? P2[r][cl] : 0.0) + p2[q][e];
+                }
+            if (dlane) {
+                const double d = de == 0 ? dg[0] : de == 1 ? dg[1] : de == 2 ? dg[2] : dg[3];
+                dts[cl] = (ww ? dts[cl] : 0.0) - d;
+            }
+        }
+        __syncthreads();
     }
     for (int idx = tid; idx < R * 16; idx += 256) {   // V[r][p] from the V^T chunks
         const int r = idx / 16, p = idx % 16;
@@ -607,7 +619,7 @@ __global__ void k_fill_zero(double* p, int64_t count)
 constexpr int ADJ_WAVES = 8;
 
 struct AdjLayout {
-    size_t zs = 0, fwd = 0, apk = 0, ckpt = 0, part = 0, tape = 0, total = 0;
+    size_t zs = 0, fwd = 0, apk = 0, ckpt = 0, gck = 0, part = 0, tape = 0, total = 0;
     int64_t nblocks = 0, nstrips = 0, nwaves = 0;
 };
 
@@ -622,16 +634,6 @@ int adj_apb(int nbw)
         case 32: return AdjGeo<32>::APB;
         case 48: return AdjGeo<48>::APB;
         default: return AdjGeo<64>::APB;
-    }
-}
-
-int adj_ppb(int nbw)
-{
-    switch (nbw) {
-        case 16: return AdjGeo<16>::PPB;
-        case 32: return AdjGeo<32>::PPB;
-        case 48: return AdjGeo<48>::PPB;
-        default: return AdjGeo<64>::PPB;
     }
 }
 
@@ -652,8 +654,8 @@ AdjLayout adj_layout(int64_t n, int nbw, int64_t nev)
         off = al(off + (size_t)L.nblocks * adj_apb(nbw) * sizeof(double));
         L.ckpt = off;
         off = al(off + (size_t)L.nblocks * nt * L.nstrips * 256 * sizeof(double));
-        L.part = off;
-        off = al(off + (size_t)L.nstrips * L.nblocks * adj_ppb(nbw) * sizeof(double));
+        L.gck = off;   // every block's output-gradient window, checkpoint layout
+        off = al(off + (size_t)L.nblocks * nt * L.nstrips * 256 * sizeof(double));
     } else {
         const int64_t nblk = (n - 2 + KB - 1) / KB;
         int64_t ckrows = 0, taperows = 0;
@@ -720,14 +722,14 @@ void blocked_backward(int64_t n, int64_t nev, const double* hv, const double* ht
                       hipStream_t st)
 {
     double* apk = (double*)(ws + L.apk);
-    double* part = (double*)(ws + L.part);
+    double* gck = (double*)(ws + L.gck);
     const unsigned nb = (unsigned)L.nblocks, ns = (unsigned)L.nstrips;
     hipLaunchKernelGGL((k_pack_adj<NB>), dim3(nb), dim3(256), 0, st, n, hv, ht, apk);
-    hipLaunchKernelGGL((k_adj_blocked<NB, ADJ_WAVES>), dim3(ns), dim3(64 * ADJ_WAVES), 0, st, n,
-                       nev, (const double*)apk, (const double*)(ws + L.ckpt), G, ldg, part,
-                       (unsigned*)ws);
-    hipLaunchKernelGGL((k_adj_finish<NB>), dim3(nb), dim3(256), 0, st, n, (int64_t)ns,
-                       (const double*)apk, (const double*)part, dv, dtau);
+    hipLaunchKernelGGL((k_adj_sweep<NB, ADJ_WAVES>), dim3(ns), dim3(64 * ADJ_WAVES), 0, st, n,
+                       nev, (const double*)apk, G, ldg, gck, (unsigned*)ws);
+    hipLaunchKernelGGL((k_adj_reduce<NB, 4>), dim3(nb), dim3(256), 0, st, n, (int64_t)ns,
+                       (const double*)apk, (const double*)(ws + L.ckpt), (const double*)gck, dv,
+                       dtau);
 }
 
 int adj_forward(int64_t n, int nbw, int64_t nev, const double* hv, const double* ht, double* Z,
