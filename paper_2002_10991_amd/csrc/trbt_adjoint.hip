@@ -135,6 +135,11 @@ __device__ inline void wave_lds_sync()
 // (J-1-j) mod NW, so slot j+1 is on the previous wave.  Per block the
 // gradient window Go becomes Gi = Q^T Go = Go - V (T^T (V^T Go)), and Go is
 // saved to gck in the checkpoint layout for the reduction pass.
+// Hand-off: a retired top tile goes to the next wave through an LDS ring
+// (counters written/consumed, back-pressure of XR tiles) when that wave holds
+// slot j-1 in the same round; through G (with the prog counters) for the
+// slot's first block (the next slot loads its first window from G), its last
+// block (the whole window is final) and across rounds.
 template <int NB, int NW>
 __global__ __launch_bounds__(64 * NW) void k_adj_sweep(int64_t n, int64_t nev,
                                                        const double* __restrict__ apk,
@@ -145,11 +150,13 @@ __global__ __launch_bounds__(64 * NW) void k_adj_sweep(int64_t n, int64_t nev,
     using A = AdjGeo<NB>;
     constexpr int NT = A::NT;
     constexpr int64_t nt1 = NB / 16;
-    __shared__ int prog[NW];
+    constexpr int XR = 3;
+    __shared__ int prog[NW], written[NW], consumed[NW];
+    __shared__ double ring[NW - 1][XR][256];
 
     const int lane = threadIdx.x & 63;
     const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-    if (threadIdx.x < NW) prog[threadIdx.x] = 0;
+    if (threadIdx.x < NW) prog[threadIdx.x] = written[threadIdx.x] = consumed[threadIdx.x] = 0;
     __syncthreads();
 
     const int64_t strip = blockIdx.x, nstrips = gridDim.x;
@@ -159,7 +166,9 @@ __global__ __launch_bounds__(64 * NW) void k_adj_sweep(int64_t n, int64_t nev,
     const bool cols_inside = (strip + 1) * 16 <= nev;
     const int rsub = lane >> 4;
     const int wprev = (w + NW - 1) % NW;
-    int seen = 0;   // last value read from prog[wprev]
+    // last values read from the counters this wave waits on (all only grow)
+    int seen = 0, seen_written = 0, seen_consumed = 0;
+    int xput = 0, xget = 0;   // ring tiles put / taken so far
 
     Tile<false> g[NT];
 
@@ -217,18 +226,40 @@ __global__ __launch_bounds__(64 * NW) void k_adj_sweep(int64_t n, int64_t nev,
             // slide down: the top tile leaves for slot j-1, a new bottom tile
             // arrives from slot j+1 (or from G when slot j+1 has no block)
             if (t > t0) {
-                store_tile<false>(g[0], G, ldg, n, nev, p0 + rsub, col,
-                                  cols_inside && p0 >= 0 && p0 + 16 <= n);
+                if (w < NW - 1 && j >= 1 && t < nblk - 1) {   // to wave w+1 through LDS
+                    if (!wait_counter(consumed, w, xput - XR + 1, err, lane, seen_consumed))
+                        return;
+                    double* dst = &ring[w][xput % XR][0];
+#pragma unroll
+                    for (int e = 0; e < 4; ++e) dst[e * 64 + lane] = g[0].re[e];
+                    ++xput;
+                    __hip_atomic_store(&written[w], xput, __ATOMIC_RELEASE,
+                                       __HIP_MEMORY_SCOPE_WORKGROUP);
+                } else {
+                    store_tile<false>(g[0], G, ldg, n, nev, p0 + rsub, col,
+                                      cols_inside && p0 >= 0 && p0 + 16 <= n);
+                }
                 __hip_atomic_store(&prog[w], base + (int)(nblk - t), __ATOMIC_RELEASE,
                                    __HIP_MEMORY_SCOPE_WORKGROUP);
 #pragma unroll
                 for (int q = 0; q + 1 < NT; ++q) g[q] = g[q + 1];
-                if (has_succ && t - 1 >= t0s &&
-                    !wait_counter(prog, wprev, base_s + (int)(nblk - (t - 1)), err, lane, seen))
-                    return;
-                const int64_t r = p0 + KB + 16 * (NT - 1);
-                const bool inside = cols_inside && r >= 0 && r + 16 <= n;
-                load_tile<false>(g[NT - 1], G, ldg, n, nev, r + rsub, col, inside);
+                if (w > 0 && has_succ && t - 1 > t0s) {   // from wave w-1's ring
+                    if (!wait_counter(written, w - 1, xget + 1, err, lane, seen_written)) return;
+                    const double* src = &ring[w - 1][xget % XR][0];
+#pragma unroll
+                    for (int e = 0; e < 4; ++e) g[NT - 1].re[e] = src[e * 64 + lane];
+                    ++xget;
+                    __hip_atomic_store(&consumed[w - 1], xget, __ATOMIC_RELEASE,
+                                       __HIP_MEMORY_SCOPE_WORKGROUP);
+                } else {
+                    if (has_succ && t - 1 >= t0s &&
+                        !wait_counter(prog, wprev, base_s + (int)(nblk - (t - 1)), err, lane,
+                                      seen))
+                        return;
+                    const int64_t r = p0 + KB + 16 * (NT - 1);
+                    const bool inside = cols_inside && r >= 0 && r + 16 <= n;
+                    load_tile<false>(g[NT - 1], G, ldg, n, nev, r + rsub, col, inside);
+                }
             } else {
 #pragma unroll
                 for (int q = 0; q < NT; ++q)
