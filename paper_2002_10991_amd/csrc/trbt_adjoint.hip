@@ -279,7 +279,7 @@ __global__ __launch_bounds__(64 * NW) void k_adj_sweep(int64_t n, int64_t nev,
 // then combined in wave order (the same result on every run); finally the
 // column-independent corrections give dv and dtau of the block's reflectors.
 template <int NB, int RW>
-__global__ __launch_bounds__(64 * RW) void k_adj_reduce(int64_t n, int64_t nstrips,
+__global__ __launch_bounds__(64 * RW, 2) void k_adj_reduce(int64_t n, int64_t nstrips,
                                                         const double* __restrict__ apk,
                                                         const double* __restrict__ ckpt,
                                                         const double* __restrict__ gck,
