@@ -201,11 +201,11 @@ struct Geo {
 //   A1 chunk lane l: A1[l%16][16q + 4u + l/16]     stored at position 4h+u
 //   -V chunk lane l: -Vt[16q + l%16][4u + l/16]    stored at position
 //                    4NT + u*NT + (NT-1-h) (real), 4NT + 4(NT-1-h) + u (complex)
-// where h = (q + rot) mod NT is the register tile that holds window tile q
-// during this block: the main kernel never moves a tile between registers,
-// the window's top tile sits in register tile rot = (-o) mod NT in the o-th
-// block of a slot.  So the chunks are stored in exactly the order the main
-// kernel consumes them.
+// where h is the register tile that holds window tile q during this block:
+// h = q for real blocks; for complex blocks h = (q + rot) mod NT, the main
+// kernel never moving a tile between registers (the window's top tile sits
+// in register tile rot = (-o) mod NT in the o-th block of a slot).  So the
+// chunks are stored in exactly the order the main kernel consumes them.
 // --------------------------------------------------------------------------
 // Shared-memory image of one block's compact-WY factor (see above).
 template <int NB, bool CPLX>
@@ -329,8 +329,8 @@ __device__ inline void pack_block(int64_t n, const double* __restrict__ hv,
     const auto& Tm = W.Tm;
     const int tid = threadIdx.x;
     // register tile of window tile 0 in this block (the block's position in
-    // its slot's sequence is W.t - W.j * NB/16)
-    const int rot = (int)((NT - (W.t - W.j * (NB / 16)) % NT) % NT);
+    // its slot's sequence is W.t - W.j * NB/16); real windows do not rotate
+    const int rot = CPLX ? (int)((NT - (W.t - W.j * (NB / 16)) % NT) % NT) : 0;
     // A1 chunks and -V chunks
     double* out = ws + (size_t)blk * G::PB;
     for (int idx = tid; idx < NT * 4 * 64; idx += 256) {
@@ -613,13 +613,17 @@ __device__ inline void lds_get(Tile<CPLX> (&t)[CT], const double* __restrict__ s
 //   chunks 4NT .. 8NT-1     -V chunks:                       Zwin += (-V) * Y
 //                           real: (u, h), u ascending, h descending;
 //                           complex: (h, u), h descending, u ascending
-// where h is a register tile.  Window tiles never move between registers
+// where h is a register tile.  Complex windows never move between registers
 // (a loop-carried rotation would cost a register copy of the whole window per
 // block): in the o-th block of a slot, window tile q (q = 0 at the top) lives
 // in register tile (q + rot) mod NT with rot = (-o) mod NT, and the pack
 // kernel stores every block's chunks in that order.  When the window slides,
-// the bottom tile (register tile rot - 1) retires and its registers take the
-// next block's top tile.
+// the bottom tile (register tile rot - 1) retires after GEMM2 and its
+// registers take the next block's top tile.  Real windows (a third of the
+// registers, and many short slots in batched use, where the hand-off latency
+// counts) keep register tile = window tile: the last MFMA of each tile writes
+// it one tile lower (zsh), and the bottom tile is handed off as soon as its
+// last MFMA is done.
 //
 // blocked_strip runs the whole back-transformation of column strip `strip`
 // (columns 16*CT*strip ..) with the NW waves of the calling workgroup; wsb
@@ -739,6 +743,7 @@ __device__ inline void blocked_strip(int64_t n, int64_t nev, const double* __res
                                         ring_re, ring_im, slot);
             };
             bool xfail = false;
+            Tile<CPLX> zsh[CPLX ? 1 : NT + 1][CT];   // real: the window after the slide
             auto store_bottom = [&](const Tile<CPLX> (&zb)[CT]) {   // the final bottom tile
                 if (!has_next) return;
                 // to wave w+1 through LDS: slot j+1 exists, is in this round, and
@@ -837,26 +842,33 @@ __device__ inline void blocked_strip(int64_t n, int64_t nev, const double* __res
                             for (int cc = 0; cc < CT; ++cc) y[0][cc].re += y[1][cc].re;
                         }
                     } else {
-                        // Zwin(tile h, :) += (-V)(tile h, chunk u) * Y(chunk u, :)
-                        const int c2 = c - 4 * NT, u = c2 / NT, h = NT - 1 - c2 % NT;
+                        // Zwin(tile q, :) += (-V)(tile q, chunk u) * Y(chunk u, :);
+                        // the last pass (u = 3) writes tile q into zsh[q+1]
+                        const int c2 = c - 4 * NT, u = c2 / NT, q = NT - 1 - c2 % NT;
 #pragma unroll
-                        for (int cc = 0; cc < CT; ++cc)
-                            zt[h][cc].re = mfma_n<0>(ar, y[0][cc].re[u], zt[h][cc].re);
+                        for (int cc = 0; cc < CT; ++cc) {
+                            const Tile<CPLX>& src = zt[q][cc];
+                            Tile<CPLX>& dst = (u == 3) ? zsh[q + 1][cc] : zt[q][cc];
+                            dst.re = mfma_n<0>(ar, y[0][cc].re[u], src.re);
+                        }
+                        if (u == 3 && q == NT - 1) store_bottom(zsh[NT]);
                     }
                 }
             }
 
-            // the bottom tile is final: hand it off; its registers take the
-            // next block's top tile
+            if constexpr (CPLX) {
+                // the bottom tile is final: hand it off; its registers take
+                // the next block's top tile
 #pragma unroll
-            for (int h = 0; h < NT; ++h)
-                if (h == ret) {
-                    store_bottom(zt[h]);
-                    if (has_next) {
+                for (int h = 0; h < NT; ++h)
+                    if (h == ret) {
+                        store_bottom(zt[h]);
+                        if (has_next) {
 #pragma unroll
-                        for (int c = 0; c < CT; ++c) zt[h][c] = znext[c];
+                            for (int c = 0; c < CT; ++c) zt[h][c] = znext[c];
+                        }
                     }
-                }
+            }
             if (xfail) return;
             if (!has_next) {
                 // the slot's last block: the whole window is final
@@ -864,9 +876,14 @@ __device__ inline void blocked_strip(int64_t n, int64_t nev, const double* __res
                 for (int h = 0; h < NT; ++h) {
                     const int q = h >= rot ? h - rot : h + NT - rot;
 #pragma unroll
-                    for (int c = 0; c < CT; ++c)
-                        store_tile<CPLX>(zt[h][c], Z, ldz, n, nev, p0 + 16 * q + rsub,
-                                         col_base + 16 * c);
+                    for (int c = 0; c < CT; ++c) {
+                        if constexpr (CPLX)
+                            store_tile<CPLX>(zt[h][c], Z, ldz, n, nev, p0 + 16 * q + rsub,
+                                             col_base + 16 * c);
+                        else
+                            store_tile<CPLX>(zsh[h + 1][c], Z, ldz, n, nev, p0 + 16 * h + rsub,
+                                             col_base + 16 * c);
+                    }
                 }
             }
             if (xin)   // the exchange tile read at the start of this block is in registers
@@ -874,7 +891,16 @@ __device__ inline void blocked_strip(int64_t n, int64_t nev, const double* __res
                                    __HIP_MEMORY_SCOPE_WORKGROUP);
             __hip_atomic_store(&prog[w], (int)(j * (nblk + 1) + t + 1), __ATOMIC_RELEASE,
                                __HIP_MEMORY_SCOPE_WORKGROUP);
-            rot = ret;
+            if constexpr (CPLX) {
+                rot = ret;
+            } else if (has_next) {
+#pragma unroll
+                for (int q = 1; q < NT; ++q)
+#pragma unroll
+                    for (int c = 0; c < CT; ++c) zt[q][c] = zsh[q][c];
+#pragma unroll
+                for (int c = 0; c < CT; ++c) zt[0][c] = znext[c];
+            }
         }
     }
 }
