@@ -678,7 +678,7 @@ AdjLayout adj_layout(int64_t n, int nbw, int64_t nev)
         const int nt = adj_tiles(nbw);
         L.nblocks = blocked_num_blocks(n, nbw);
         L.nstrips = (nev + 15) / 16;
-        const size_t pb = (size_t)2 * nt * 4 * 64;
+        const size_t pb = (size_t)packed_block_doubles(nbw, false);
         L.fwd = off;
         off = al(off + (size_t)L.nblocks * pb * sizeof(double));
         L.apk = off;

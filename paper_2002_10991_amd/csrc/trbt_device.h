@@ -943,13 +943,25 @@ inline int check_device()
 
 inline bool blocked_eligible(int nbw) { return nbw == 16 || nbw == 32 || nbw == 48 || nbw == 64; }
 
+// Doubles per packed block: the pack kernel's layout, Geo<NB, CPLX>::PB, is
+// the only definition (workspace sizes and stream limits derive from it).
+inline int64_t packed_block_doubles(int nbw, bool cplx)
+{
+    switch (nbw) {
+        case 16: return cplx ? Geo<16, true>::PB : Geo<16, false>::PB;
+        case 32: return cplx ? Geo<32, true>::PB : Geo<32, false>::PB;
+        case 48: return cplx ? Geo<48, true>::PB : Geo<48, false>::PB;
+        case 64: return cplx ? Geo<64, true>::PB : Geo<64, false>::PB;
+        default: return 0;
+    }
+}
+
 // The blocked kernels address one slot's operand stream (at most
 // ceil((n-2)/16) blocks) through a 32-bit buffer range.
 inline bool blocked_fits(int64_t n, int nbw, bool cplx)
 {
     const int64_t nblk = (n - 2 + KB - 1) / KB;
-    const int64_t pb = (int64_t)2 * (nbw / 16 + 1) * 4 * 64 * (cplx ? 2 : 1);
-    return nblk * pb * (int64_t)sizeof(double) < ((int64_t)1 << 31);
+    return nblk * packed_block_doubles(nbw, cplx) * (int64_t)sizeof(double) < ((int64_t)1 << 31);
 }
 
 // Problems the blocked (compact-WY, MFMA) kernels take; the rest run the
@@ -961,9 +973,9 @@ inline bool use_blocked(int64_t n, int nbw, bool cplx)
 
 inline size_t blocked_bytes(int64_t n, int nbw, bool cplx)
 {
-    const int nt = nbw / 16 + 1;
-    const size_t pb = (size_t)2 * nt * 4 * 64 * (cplx ? 2 : 1);
-    return HDR_BYTES + (size_t)blocked_num_blocks(n, nbw) * pb * sizeof(double);
+    return HDR_BYTES +
+           (size_t)blocked_num_blocks(n, nbw) * (size_t)packed_block_doubles(nbw, cplx) *
+               sizeof(double);
 }
 
 inline int validate(int64_t n, int nbw, int64_t nev, const void* hv, const void* ht,
