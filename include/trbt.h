@@ -141,8 +141,8 @@ int trbt_apply_z(int64_t n, int nbw, int64_t nev, const trbt_z *hh_v, const trbt
 /* Workspace bytes for the adjoint of (n, nbw, nev); ckpt_every is 0 or 16
  * (the default, and the only interval implemented).  Errors: -1 n, -2 nbw,
  * -3 nev, -4 ckpt_every, -5 null `bytes`.  The workspace is large: the
- * checkpoints hold about n^2/(2 nbw) * (nbw + 16) * nev / 16 doubles and
- * the per-strip column sums a similar amount. */
+ * checkpoints hold about n^2/(2 nbw) * (nbw + 16) * nev / 16 doubles, and
+ * the backward pass saves the gradient windows in as many again. */
 int trbt_adjoint_workspace_bytes_d(int64_t n, int nbw, int64_t nev, int ckpt_every,
                                    size_t *bytes);
 
