@@ -140,26 +140,36 @@ __device__ inline void wave_lds_sync()
 // slot j-1 in the same round; through G (with the prog counters) for the
 // slot's first block (the next slot loads its first window from G), its last
 // block (the whole window is final) and across rounds.
+// Per-workgroup LDS state of the sweep: progress counters and the
+// wave-to-wave exchange ring (zero counters on entry).
+template <int NW>
+struct SweepLds {
+    static constexpr int XR = 3;
+    int prog[NW], written[NW], consumed[NW];
+    double ring[NW - 1][XR][256];
+    __device__ void reset()
+    {
+        if (threadIdx.x < NW) prog[threadIdx.x] = written[threadIdx.x] = consumed[threadIdx.x] = 0;
+    }
+};
+
 template <int NB, int NW>
-__global__ __launch_bounds__(64 * NW) void k_adj_sweep(int64_t n, int64_t nev,
-                                                       const double* __restrict__ apk,
-                                                       double* __restrict__ G, int64_t ldg,
-                                                       double* __restrict__ gck,
-                                                       unsigned* __restrict__ err)
+__device__ __attribute__((always_inline)) inline void adj_sweep_strip(int64_t n, int64_t nev, const double* __restrict__ apk,
+                                       double* __restrict__ G, int64_t ldg,
+                                       double* __restrict__ gck, unsigned* __restrict__ err,
+                                       int64_t strip, int64_t nstrips, SweepLds<NW>& S)
 {
     using A = AdjGeo<NB>;
     constexpr int NT = A::NT;
     constexpr int64_t nt1 = NB / 16;
-    constexpr int XR = 3;
-    __shared__ int prog[NW], written[NW], consumed[NW];
-    __shared__ double ring[NW - 1][XR][256];
+    constexpr int XR = SweepLds<NW>::XR;
+    int* prog = S.prog;
+    int* written = S.written;
+    int* consumed = S.consumed;
+    auto& ring = S.ring;
 
     const int lane = threadIdx.x & 63;
     const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-    if (threadIdx.x < NW) prog[threadIdx.x] = written[threadIdx.x] = consumed[threadIdx.x] = 0;
-    __syncthreads();
-
-    const int64_t strip = blockIdx.x, nstrips = gridDim.x;
     const int64_t nblk = (n - 2 + KB - 1) / KB;
     const int64_t J = sweeps_in_stage(n, NB, 0);
     const int64_t col = strip * 16 + (lane & 15);
@@ -268,6 +278,51 @@ __global__ __launch_bounds__(64 * NW) void k_adj_sweep(int64_t n, int64_t nev,
                                    __HIP_MEMORY_SCOPE_WORKGROUP);
             }
         }
+    }
+}
+
+template <int NB, int NW>
+__global__ __launch_bounds__(64 * NW) void k_adj_sweep(int64_t n, int64_t nev,
+                                                       const double* __restrict__ apk,
+                                                       double* __restrict__ G, int64_t ldg,
+                                                       double* __restrict__ gck,
+                                                       unsigned* __restrict__ err)
+{
+    __shared__ SweepLds<NW> S;
+    S.reset();
+    __syncthreads();
+    adj_sweep_strip<NB, NW>(n, nev, apk, G, ldg, gck, err, blockIdx.x, gridDim.x, S);
+}
+
+// The one-call adjoint runs the checkpointing forward and the sweep in one
+// launch: they are independent (the sweep needs only G and the adjoint
+// packs), and each has only one workgroup per column strip, so together
+// they fill twice as many CUs.  Workgroups [0, ns) run the forward,
+// [ns, 2 ns) the sweep.
+template <int NB, int NW>
+__global__ __launch_bounds__(64 * NW) void k_adj_fwd_sweep(int64_t n, int64_t nev,
+                                                           const double* __restrict__ blocks,
+                                                           double* __restrict__ Z, int64_t ldz,
+                                                           double* __restrict__ ckpt,
+                                                           const double* __restrict__ apk,
+                                                           double* __restrict__ G, int64_t ldg,
+                                                           double* __restrict__ gck,
+                                                           unsigned* __restrict__ err)
+{
+    __shared__ union {
+        StripLds<NB, 1, false, NW> f;
+        SweepLds<NW> b;
+    } U;
+    const int64_t ns = gridDim.x / 2;
+    if ((int64_t)blockIdx.x < ns) {
+        U.f.reset();
+        __syncthreads();
+        blocked_strip<NB, 1, false, ring_depth<NB, false>(), NW, true>(
+            n, nev, blocks, Z, ldz, err, blockIdx.x, U.f, ckpt, ns);
+    } else {
+        U.b.reset();
+        __syncthreads();
+        adj_sweep_strip<NB, NW>(n, nev, apk, G, ldg, gck, err, blockIdx.x - ns, ns, U.b);
     }
 }
 
@@ -763,6 +818,27 @@ void blocked_backward(int64_t n, int64_t nev, const double* hv, const double* ht
                        dtau);
 }
 
+// Both halves in one go (the one-call adjoint): the checkpointing forward and
+// the backward sweep share one launch, then the reduction.
+template <int NB>
+void blocked_both(int64_t n, int64_t nev, const double* hv, const double* ht, double* Z,
+                  int64_t ldz, double* G, int64_t ldg, double* dv, double* dtau, char* ws,
+                  const AdjLayout& L, hipStream_t st)
+{
+    double* fwd = (double*)(ws + L.fwd);
+    double* apk = (double*)(ws + L.apk);
+    double* gck = (double*)(ws + L.gck);
+    const unsigned nb = (unsigned)L.nblocks, ns = (unsigned)L.nstrips;
+    hipLaunchKernelGGL((k_pack<NB, false>), dim3(nb), dim3(256), 0, st, n, hv, ht, fwd);
+    hipLaunchKernelGGL((k_pack_adj<NB>), dim3(nb), dim3(256), 0, st, n, hv, ht, apk);
+    hipLaunchKernelGGL((k_adj_fwd_sweep<NB, ADJ_WAVES>), dim3(2 * ns), dim3(64 * ADJ_WAVES), 0,
+                       st, n, nev, (const double*)fwd, Z, ldz, (double*)(ws + L.ckpt),
+                       (const double*)apk, G, ldg, gck, (unsigned*)ws);
+    hipLaunchKernelGGL((k_adj_reduce<NB, 4>), dim3(nb), dim3(256), 0, st, n, (int64_t)ns,
+                       (const double*)apk, (const double*)(ws + L.ckpt), (const double*)gck, dv,
+                       dtau);
+}
+
 int adj_forward(int64_t n, int nbw, int64_t nev, const double* hv, const double* ht, double* Z,
                 int64_t ldz, char* ws, const AdjLayout& L, hipStream_t st)
 {
@@ -854,6 +930,16 @@ int trans_ev_tridi_to_band_adjoint_d(int64_t n, int nbw, int64_t nev, const doub
                          (size_t)n * sizeof(double), (size_t)nev, hipMemcpyDeviceToDevice,
                          st) != hipSuccess)
         return TRBT_ERR_HIP;
+    if (use_blocked(n, nbw, false)) {
+        switch (nbw) {
+            case 16: blocked_both<16>(n, nev, hh_v, hh_tau, Zs, n, G, ldg, dv, dtau, ws, L, st); break;
+            case 32: blocked_both<32>(n, nev, hh_v, hh_tau, Zs, n, G, ldg, dv, dtau, ws, L, st); break;
+            case 48: blocked_both<48>(n, nev, hh_v, hh_tau, Zs, n, G, ldg, dv, dtau, ws, L, st); break;
+            case 64: blocked_both<64>(n, nev, hh_v, hh_tau, Zs, n, G, ldg, dv, dtau, ws, L, st); break;
+            default: return TRBT_ERR_INTERNAL;
+        }
+        return hipGetLastError() == hipSuccess ? TRBT_SUCCESS : TRBT_ERR_HIP;
+    }
     rc = adj_forward(n, nbw, nev, hh_v, hh_tau, Zs, n, ws, L, st);
     if (rc) return rc;
     return adj_backward(n, nbw, nev, hh_v, hh_tau, G, ldg, dv, dtau, ws, L, st);

@@ -638,7 +638,7 @@ __device__ inline void lds_get(Tile<CPLX> (&t)[CT], const double* __restrict__ s
 //   ckpt[(((b * NT + q) * nstrips + strip) * 4 + e) * 64 + lane]
 // b = the block's slot-major index, q = tile of the window, e = element.
 template <int NB, int CT, bool CPLX, int D, int NW, bool CKPT = false>
-__device__ inline void blocked_strip(int64_t n, int64_t nev, const double* __restrict__ wsb,
+__device__ __attribute__((always_inline)) inline void blocked_strip(int64_t n, int64_t nev, const double* __restrict__ wsb,
                                      double* __restrict__ Z, int64_t ldz,
                                      unsigned* __restrict__ err, int64_t strip,
                                      StripLds<NB, CT, CPLX, NW>& S,
