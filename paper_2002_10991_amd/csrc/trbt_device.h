@@ -759,7 +759,11 @@ __device__ __attribute__((always_inline)) inline void blocked_strip(int64_t n, i
                     __hip_atomic_store(&S.written[w], xput, __ATOMIC_RELEASE,
                                        __HIP_MEMORY_SCOPE_WORKGROUP);
                 } else {
-                    const int64_t rb = p0 + 16 * (NT - 1);
+                    // complex: opaque to the optimizer, so that the
+                    // addressing of this rare path is not hoisted out of the
+                    // per-register-tile hand-off sites into every block
+                    int64_t rb = p0 + 16 * (NT - 1);
+                    if constexpr (CPLX) asm volatile("" : "+s"(rb));
                     const bool inside = cols_inside && rb >= 0 && rb + 16 <= n;
 #pragma unroll
                     for (int cc = 0; cc < CT; ++cc)
