@@ -108,6 +108,20 @@ def test_workspace_query(T):
         T.trbt_workspace_bytes(10, 300, 1, False)
 
 
+@pytest.mark.parametrize("n,nbw", [(1000, 64), (2000, 32), (777, 48), (300, 16), (66, 64)])
+def test_workspace_size_is_the_packed_layout(T, oracle_mod, n, nbw):
+    """Blocked shapes: a 256-byte header plus, for every (slot j, 16-stage
+    block t >= j*nbw/16), the two MFMA operand matrices of the block's
+    compact-WY factor, (nbw+16) x 16 each, one plane real, two complex."""
+    st = oracle_mod.reflector_table(n, nbw)[0]
+    J = int(np.sum(st == 0))                   # slots of stage 0
+    nblk = -(-(n - 2) // 16)
+    nblocks = sum(nblk - j * (nbw // 16) for j in range(J))
+    for cplx, planes in ((False, 1), (True, 2)):
+        expect = 256 + nblocks * 2 * (nbw + 16) * 16 * planes * 8
+        assert T.trbt_workspace_bytes(n, nbw, 10, cplx) == expect, (n, nbw, cplx)
+
+
 def test_strerror(T):
     assert T.trbt_strerror(0) == "success"
     assert "gfx950" in T.trbt_strerror(-100)
