@@ -291,26 +291,31 @@ __device__ inline void wy_factor(int64_t n, const double* __restrict__ hv,
         if (CPLX) Tm[a][b][NC - 1] = (a == b) ? tau[a][NC - 1] : 0.0;
     }
     __syncthreads();
-    for (int q = 1; q < 16; ++q) {   // column q of T from columns 0..q-1
-        if (tid < q) {
-            const int p = tid;
-            double wr = 0.0, wi = 0.0;   // w = sum_{i=p}^{q-1} T[p][i] Gm[i][q]
-            for (int i = p; i < q; ++i) {
-                const double tr = Tm[p][i][0], gr = Gm[i][q][0];
+    // T = (I + D N)^{-1} D with D = diag(tau) and N the strictly upper part
+    // of V^H V (the same T as the column recursion T[0:q,q] =
+    // -tau_q T[0:q,0:q] V^H v_q, also for tau = 0): column p by back
+    // substitution, T[i][p] = -tau_i sum_{k=i+1..p} Gm[i][k] T[k][p], one
+    // thread per column and no barrier between the steps.
+    if (tid < 16) {
+        const int p = tid;
+        for (int i = p - 1; i >= 0; --i) {
+            double wr = 0.0, wi = 0.0;   // w = sum_{k=i+1}^{p} Gm[i][k] T[k][p]
+            for (int k = i + 1; k <= p; ++k) {
+                const double gr = Gm[i][k][0], tr = Tm[k][p][0];
                 if (CPLX) {
-                    const double ti = Tm[p][i][NC - 1], gi = Gm[i][q][NC - 1];
-                    wr += tr * gr - ti * gi;
-                    wi += tr * gi + ti * gr;
+                    const double gi = Gm[i][k][NC - 1], ti = Tm[k][p][NC - 1];
+                    wr += gr * tr - gi * ti;
+                    wi += gr * ti + gi * tr;
                 } else {
-                    wr += tr * gr;
+                    wr += gr * tr;
                 }
             }
-            const double ur = tau[q][0], ui = CPLX ? tau[q][NC - 1] : 0.0;
-            Tm[p][q][0] = -(ur * wr - ui * wi);
-            if (CPLX) Tm[p][q][NC - 1] = -(ur * wi + ui * wr);
+            const double ur = tau[i][0], ui = CPLX ? tau[i][NC - 1] : 0.0;
+            Tm[i][p][0] = -(ur * wr - ui * wi);
+            if (CPLX) Tm[i][p][NC - 1] = -(ur * wi + ui * wr);
         }
-        __syncthreads();
     }
+    __syncthreads();
 }
 
 // pack_block packs block `blk` (slot-major numbering) of one problem into
