@@ -191,9 +191,10 @@ int trans_ev_tridi_to_band_bwd_ckpt_d(int64_t n, int nbw, int64_t nev,
                                       void *stream);
 
 /* ------------------------------------------------------------------------
- * Batched back-transformation: many independent real problems of uneven
- * size (k-points, spin channels), each exactly the operation above, run
- * through one persistent launch per band width, captured once in a HIP graph.
+ * Batched back-transformation: many independent problems of uneven size
+ * (k-points, spin channels), all real or all complex, each exactly the
+ * operation above, run through one persistent launch per band width,
+ * captured once in a HIP graph.
  * ------------------------------------------------------------------------ */
 
 /* One problem: the arguments of trans_ev_tridi_to_band_d.  All pointers are
@@ -223,6 +224,19 @@ typedef struct {
     int block_stages;
 } trbt_plan_config;
 
+/* One complex problem: the arguments of trans_ev_tridi_to_band_z.  A plan
+ * holds real problems only (trbt_plan_create_batched_d) or complex problems
+ * only (trbt_plan_create_batched_z). */
+typedef struct {
+    int64_t n;
+    int nbw;
+    int64_t nev;
+    const trbt_z *hh_v;
+    const trbt_z *hh_tau;
+    trbt_z *Z;
+    int64_t ldz;
+} trbt_problem_z;
+
 typedef struct trbt_plan trbt_plan;   /* opaque */
 
 /* Status of a problem descriptor that fails the single-call checks. */
@@ -244,6 +258,14 @@ typedef struct trbt_plan trbt_plan;   /* opaque */
  * block_stages 16, and block_stages 1 when no problem can take the blocked
  * form or every problem has n <= 256. */
 int trbt_plan_create_batched_d(const trbt_problem_d *probs, int count,
+                               const trbt_plan_config *cfg, trbt_plan **plan,
+                               void *stream);
+
+/* The same for complex Hermitian problems (the operation of
+ * trans_ev_tridi_to_band_z per problem).  Complex plans use 16-column
+ * strips: strip_cols 32 is rejected (-3) and not among the tuning
+ * candidates.  Arguments and status codes otherwise as above. */
+int trbt_plan_create_batched_z(const trbt_problem_z *probs, int count,
                                const trbt_plan_config *cfg, trbt_plan **plan,
                                void *stream);
 

@@ -20,9 +20,9 @@ __all__ = [
     "TrbtError", "lib", "trbt_num_reflectors", "trbt_stage_offsets", "trbt_workspace_bytes",
     "trans_ev_tridi_to_band_d", "trans_ev_tridi_to_band_z", "trbt_prepare_d", "trbt_prepare_z",
     "trbt_apply_d", "trbt_apply_z", "trbt_strerror", "back_transform", "alloc_workspace",
-    "TRBT_WORK_ALIGN", "TRBT_NBW_MAX", "trbt_problem_d", "trbt_plan_config",
-    "trbt_plan_create_batched_d", "trbt_plan_exec", "trbt_plan_get_config", "trbt_plan_check",
-    "trbt_plan_destroy", "BatchedPlan", "trbt_adjoint_workspace_bytes_d",
+    "TRBT_WORK_ALIGN", "TRBT_NBW_MAX", "trbt_problem_d", "trbt_problem_z", "trbt_plan_config",
+    "trbt_plan_create_batched_d", "trbt_plan_create_batched_z", "trbt_plan_exec",
+    "trbt_plan_get_config", "trbt_plan_check", "trbt_plan_destroy", "BatchedPlan", "trbt_adjoint_workspace_bytes_d",
     "trans_ev_tridi_to_band_adjoint_d", "trans_ev_tridi_to_band_fwd_ckpt_d",
     "trans_ev_tridi_to_band_bwd_ckpt_d", "adjoint", "BackTransform", "back_transform_autograd",
 ]
@@ -36,6 +36,13 @@ _lib = None
 
 class trbt_problem_d(C.Structure):
     """One problem of a batched plan (device pointers as integers)."""
+    _fields_ = [("n", C.c_int64), ("nbw", C.c_int), ("nev", C.c_int64),
+                ("hh_v", C.c_void_p), ("hh_tau", C.c_void_p), ("Z", C.c_void_p),
+                ("ldz", C.c_int64)]
+
+
+class trbt_problem_z(C.Structure):
+    """One complex problem of a batched plan (device pointers as integers)."""
     _fields_ = [("n", C.c_int64), ("nbw", C.c_int), ("nev", C.c_int64),
                 ("hh_v", C.c_void_p), ("hh_tau", C.c_void_p), ("Z", C.c_void_p),
                 ("ldz", C.c_int64)]
@@ -84,6 +91,10 @@ def lib():
                                                  C.POINTER(trbt_plan_config),
                                                  C.POINTER(vp), vp]
         L.trbt_plan_create_batched_d.restype = i32
+        L.trbt_plan_create_batched_z.argtypes = [C.POINTER(trbt_problem_z), i32,
+                                                 C.POINTER(trbt_plan_config),
+                                                 C.POINTER(vp), vp]
+        L.trbt_plan_create_batched_z.restype = i32
         L.trbt_plan_exec.argtypes = [vp, vp]
         L.trbt_plan_exec.restype = i32
         L.trbt_plan_get_config.argtypes = [vp, C.POINTER(trbt_plan_config),
@@ -218,21 +229,29 @@ def back_transform(Z, hh_v, hh_tau, nbw: int, work=None, stream=None):
 # --------------------------------------------------------------------------
 # Batched plans
 # --------------------------------------------------------------------------
-def trbt_plan_create_batched_d(probs, cfg=None, stream=None):
-    """probs: sequence of trbt_problem_d (or of tuples in its field order).
-    cfg: None (autotune) or trbt_plan_config / (strip_cols, waves, block_stages).
-    Returns (status, plan handle or None)."""
-    arr = (trbt_problem_d * max(len(probs), 1))()
+def _plan_create(fn, struct, probs, cfg, stream):
+    arr = (struct * max(len(probs), 1))()
     for i, p in enumerate(probs):
-        arr[i] = p if isinstance(p, trbt_problem_d) else trbt_problem_d(*p)
+        arr[i] = p if isinstance(p, struct) else struct(*p)
     c = None
     if cfg is not None:
         c = cfg if isinstance(cfg, trbt_plan_config) else trbt_plan_config(*cfg)
     h = C.c_void_p()
-    rc = lib().trbt_plan_create_batched_d(arr if probs else None, len(probs),
-                                          C.byref(c) if c is not None else None, C.byref(h),
-                                          _stream(stream))
+    rc = fn(arr if probs else None, len(probs), C.byref(c) if c is not None else None,
+            C.byref(h), _stream(stream))
     return rc, (h.value if rc == 0 else None)
+
+
+def trbt_plan_create_batched_d(probs, cfg=None, stream=None):
+    """probs: sequence of trbt_problem_d (or of tuples in its field order).
+    cfg: None (autotune) or trbt_plan_config / (strip_cols, waves, block_stages).
+    Returns (status, plan handle or None)."""
+    return _plan_create(lib().trbt_plan_create_batched_d, trbt_problem_d, probs, cfg, stream)
+
+
+def trbt_plan_create_batched_z(probs, cfg=None, stream=None):
+    """The same for complex problems (sequence of trbt_problem_z)."""
+    return _plan_create(lib().trbt_plan_create_batched_z, trbt_problem_z, probs, cfg, stream)
 
 
 def trbt_plan_exec(plan, stream=None) -> int:
@@ -263,33 +282,36 @@ def trbt_plan_destroy(plan) -> int:
 class BatchedPlan:
     """A batched plan over torch tensors.
 
-    problems: list of (Z, hh_v, hh_tau, nbw) with Z an (n, nev) float64
-    column-major view (unit row stride) and hh_v (K, nbw), hh_tau (K,)
-    contiguous float64, all on the current device.  The tensors must stay
-    alive (same storage) for the plan's lifetime; their contents may change
-    between runs."""
+    problems: list of (Z, hh_v, hh_tau, nbw) with Z an (n, nev) column-major
+    view (unit row stride) and hh_v (K, nbw), hh_tau (K,) contiguous, all
+    float64 (a real plan) or all complex128 (a complex plan), on the current
+    device.  The tensors must stay alive (same storage) for the plan's
+    lifetime; their contents may change between runs."""
 
     def __init__(self, problems, cfg=None, stream=None):
         import torch
         descs = []
         self._keep = []
+        dtypes = {t.dtype for Z, hv, ht, nbw in problems for t in (Z, hv, ht)}
+        if not dtypes <= {torch.float64} and not dtypes <= {torch.complex128}:
+            raise TypeError("batched plans are all float64 or all complex128")
+        cplx = dtypes == {torch.complex128}
+        struct = trbt_problem_z if cplx else trbt_problem_d
         for Z, hv, ht, nbw in problems:
             n, nev = Z.shape
             if nev and n and Z.stride(0) != 1:
                 raise ValueError("Z must be column-major (unit row stride)")
-            for t in (Z, hv, ht):
-                if t.dtype != torch.float64:
-                    raise TypeError("batched plans are real FP64")
             if not hv.is_contiguous() or not ht.is_contiguous():
                 raise TypeError("hh_v and hh_tau must be contiguous")
             ldz = Z.stride(1) if nev > 1 else max(n, 1)
-            descs.append(trbt_problem_d(n, nbw, nev, _ptr(hv) if hv.numel() else None,
-                                        _ptr(ht) if ht.numel() else None,
-                                        _ptr(Z) if Z.numel() else None, max(ldz, 1)))
+            descs.append(struct(n, nbw, nev, _ptr(hv) if hv.numel() else None,
+                                _ptr(ht) if ht.numel() else None,
+                                _ptr(Z) if Z.numel() else None, max(ldz, 1)))
             self._keep.append((Z, hv, ht))
-        rc, self.handle = trbt_plan_create_batched_d(descs, cfg, stream)
+        create = trbt_plan_create_batched_z if cplx else trbt_plan_create_batched_d
+        rc, self.handle = create(descs, cfg, stream)
         if rc:
-            raise TrbtError(rc, "trbt_plan_create_batched_d")
+            raise TrbtError(rc, create.__name__)
 
     @property
     def config(self):

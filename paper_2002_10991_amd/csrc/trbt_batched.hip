@@ -1,6 +1,6 @@
-// trbt_batched.hip -- batched back-transformation of many independent real
-// eigenproblems of uneven size (k-points, spin channels) in one persistent,
-// graph-captured launch per band width.
+// trbt_batched.hip -- batched back-transformation of many independent
+// eigenproblems of uneven size (k-points, spin channels), all real or all
+// complex Hermitian, in one persistent, graph-captured launch per band width.
 //
 // The operation per problem is the single-problem one (Yu et al., CPC 2020,
 // Sec. 2.2.2, Eq. 2stage_bkwd1): columns are independent and the reflector
@@ -28,10 +28,10 @@
 // trbt_plan_exec.
 //
 // Tuning: without a fixed configuration, plan creation times every
-// candidate (strip width 16 or 32 columns, 4 or 8 waves per workgroup,
-// 16-stage compact-WY blocks; one reflector at a time as well when no
-// problem can take the blocked form or all have n <= 256) on scratch copies
-// of the problems' Z and keeps the fastest.
+// candidate (strip width 16 or 32 columns (complex: 16), 4 or 8 waves per
+// workgroup, 16-stage compact-WY blocks; one reflector at a time as well
+// when no problem can take the blocked form or all have n <= 256) on scratch
+// copies of the problems' Z and keeps the fastest.
 
 #include <hip/hip_runtime.h>
 
@@ -52,7 +52,7 @@ constexpr int QSTRIDE = 16;         // ints between two queue counters (64 B)
 constexpr int MAX_GROUPS = 5;       // nbw 16, 32, 48, 64 blocked + streaming
 constexpr size_t HDR = 256 + MAX_GROUPS * NXCD * QSTRIDE * sizeof(int);
 
-struct BProb {
+struct BProb {   // complex problems: interleaved (re, im) doubles
     int64_t n, nev, ldz;
     const double* hv;
     const double* ht;
@@ -76,27 +76,27 @@ __device__ inline int find_problem(const BProb* __restrict__ probs, int nprob, i
     return lo;
 }
 
-template <int NB>
+template <int NB, bool CPLX>
 __global__ __launch_bounds__(256) void k_pack_batched(const BProb* __restrict__ probs, int nprob)
 {
     __shared__ int s_p;
     if (threadIdx.x == 0) s_p = find_problem(probs, nprob, blockIdx.x);
     __syncthreads();
     const BProb& P = probs[s_p];
-    pack_block<NB, false>(P.n, P.hv, P.ht, P.ws, (int64_t)blockIdx.x - P.first);
+    pack_block<NB, CPLX>(P.n, P.hv, P.ht, P.ws, (int64_t)blockIdx.x - P.first);
 }
 
 // Persistent blocked kernel: one (problem, strip) task at a time per
 // workgroup until every queue is empty.
-template <int NB, int CT, int NW>
+template <int NB, int CT, int NW, bool CPLX>
 __global__ __launch_bounds__(64 * NW) void k_blocked_batched(const BProb* __restrict__ probs,
                                                              const BTask* __restrict__ tasks,
                                                              const int* __restrict__ qbegin,
                                                              int* __restrict__ qnext,
                                                              unsigned* __restrict__ err)
 {
-    constexpr int D = ring_depth<NB, false, CT>();
-    __shared__ StripLds<NB, CT, false, NW> S;
+    constexpr int D = ring_depth<NB, CPLX, CT>();
+    __shared__ StripLds<NB, CT, CPLX, NW> S;
     __shared__ int s_task;
     const int home = blockIdx.x % NXCD;
     for (;;) {
@@ -120,19 +120,21 @@ __global__ __launch_bounds__(64 * NW) void k_blocked_batched(const BProb* __rest
         if (task < 0) return;
         const BTask tk = tasks[task];
         const BProb& P = probs[tk.prob];
-        blocked_strip<NB, CT, false, D, NW>(P.n, P.nev, P.ws, P.Z, P.ldz, err, tk.strip, S);
+        blocked_strip<NB, CT, CPLX, D, NW>(P.n, P.nev, P.ws, P.Z, P.ldz, err, tk.strip, S);
         __syncthreads();
     }
 }
 
 // Streaming form: one lane per column, problems back to back in the grid.
+template <typename T>
 __global__ __launch_bounds__(64) void k_unblocked_batched(const BProb* __restrict__ probs,
                                                           int nprob)
 {
     const BProb& P = probs[find_problem(probs, nprob, blockIdx.x)];
     const int64_t col = ((int64_t)blockIdx.x - P.first) * 64 + threadIdx.x;
     if (col >= P.nev) return;
-    unblocked_column<double>(P.n, (int)P.nbw, P.hv, P.ht, P.Z + col * P.ldz);
+    unblocked_column<T>(P.n, (int)P.nbw, (const T*)P.hv, (const T*)P.ht,
+                        (T*)P.Z + col * P.ldz);
 }
 
 // --------------------------------------------------------------------------
@@ -151,10 +153,10 @@ struct Group {
     int64_t apply_grid = 0;
 };
 
-bool valid_config(const trbt_plan_config& c)
+bool valid_config(const trbt_plan_config& c, bool cplx)
 {
-    return (c.strip_cols == 16 || c.strip_cols == 32) && (c.waves == 4 || c.waves == 8) &&
-           (c.block_stages == 16 || c.block_stages == 1);
+    return (c.strip_cols == 16 || (c.strip_cols == 32 && !cplx)) &&
+           (c.waves == 4 || c.waves == 8) && (c.block_stages == 16 || c.block_stages == 1);
 }
 
 }  // namespace
@@ -162,7 +164,8 @@ bool valid_config(const trbt_plan_config& c)
 struct trbt_plan {
     int device = 0;
     int cus = 0;
-    std::vector<trbt_problem_d> probs;
+    bool cplx = false;                 // all problems complex (else all real)
+    std::vector<trbt_problem_d> probs; // complex: pointers to interleaved doubles
     std::vector<size_t> ws_off;   // packed-block offset of each problem (or 0)
     size_t ws_bytes = 0;          // total packed-block bytes
     size_t table_off = 0;         // start of the tables region
@@ -178,18 +181,19 @@ struct trbt_plan {
 
 namespace {
 
-int64_t problem_cost(const trbt_problem_d& p)
+int64_t problem_cost(const trbt_problem_d& p, bool cplx)
 {   // MFMA work of one strip ~ number of packed blocks; streaming ~ L
-    return use_blocked(p.n, p.nbw, false) ? blocked_num_blocks(p.n, p.nbw)
-                                   : num_reflectors(p.n, p.nbw) * p.nbw / 16;
+    return use_blocked(p.n, p.nbw, cplx) ? blocked_num_blocks(p.n, p.nbw)
+                                         : num_reflectors(p.n, p.nbw) * p.nbw / 16;
 }
 
-template <int NB, int CT, int NW>
+template <int NB, int CT, int NW, bool CPLX>
 int occupancy_grid(int cus, int64_t ntasks, int64_t* grid)
 {
     int per_cu = 0;
     if (hipOccupancyMaxActiveBlocksPerMultiprocessor(
-            &per_cu, (const void*)k_blocked_batched<NB, CT, NW>, 64 * NW, 0) != hipSuccess)
+            &per_cu, (const void*)k_blocked_batched<NB, CT, NW, CPLX>, 64 * NW, 0) !=
+        hipSuccess)
         return TRBT_ERR_HIP;
     if (per_cu < 1) per_cu = 1;
     const int64_t slots = (int64_t)per_cu * cus;
@@ -197,10 +201,10 @@ int occupancy_grid(int cus, int64_t ntasks, int64_t* grid)
     return TRBT_SUCCESS;
 }
 
-template <int NB, int CT, int NW>
+template <int NB, int CT, int NW, bool CPLX>
 void launch_blocked(const Group& g, char* dmem, unsigned* err, int* qnext, hipStream_t st)
 {
-    hipLaunchKernelGGL((k_blocked_batched<NB, CT, NW>), dim3((unsigned)g.apply_grid),
+    hipLaunchKernelGGL((k_blocked_batched<NB, CT, NW, CPLX>), dim3((unsigned)g.apply_grid),
                        dim3(64 * NW), 0, st, (const BProb*)(dmem + g.off_probs),
                        (const BTask*)(dmem + g.off_tasks), (const int*)(dmem + g.off_qbegin),
                        qnext, err);
@@ -211,18 +215,28 @@ int dispatch_blocked(const trbt_plan& P, const Group& g, unsigned* err, int* qne
                      hipStream_t st, bool grid_only, int64_t* grid)
 {
     const int CT = P.cfg.strip_cols / 16, NW = P.cfg.waves;
-    if (grid_only) {
-        if (CT == 1 && NW == 4) return occupancy_grid<NB, 1, 4>(P.cus, g.ntasks, grid);
-        if (CT == 1 && NW == 8) return occupancy_grid<NB, 1, 8>(P.cus, g.ntasks, grid);
-        if (CT == 2 && NW == 4) return occupancy_grid<NB, 2, 4>(P.cus, g.ntasks, grid);
-        return occupancy_grid<NB, 2, 8>(P.cus, g.ntasks, grid);
+    if (P.cplx) {   // complex: one 16-column tile per wave
+        if (grid_only)
+            return NW == 4 ? occupancy_grid<NB, 1, 4, true>(P.cus, g.ntasks, grid)
+                           : occupancy_grid<NB, 1, 8, true>(P.cus, g.ntasks, grid);
+        hipLaunchKernelGGL((k_pack_batched<NB, true>), dim3((unsigned)g.grid), dim3(256), 0, st,
+                           (const BProb*)(P.dmem + g.off_probs), (int)g.members.size());
+        if (NW == 4) launch_blocked<NB, 1, 4, true>(g, P.dmem, err, qnext, st);
+        else launch_blocked<NB, 1, 8, true>(g, P.dmem, err, qnext, st);
+        return TRBT_SUCCESS;
     }
-    hipLaunchKernelGGL((k_pack_batched<NB>), dim3((unsigned)g.grid), dim3(256), 0, st,
+    if (grid_only) {
+        if (CT == 1 && NW == 4) return occupancy_grid<NB, 1, 4, false>(P.cus, g.ntasks, grid);
+        if (CT == 1 && NW == 8) return occupancy_grid<NB, 1, 8, false>(P.cus, g.ntasks, grid);
+        if (CT == 2 && NW == 4) return occupancy_grid<NB, 2, 4, false>(P.cus, g.ntasks, grid);
+        return occupancy_grid<NB, 2, 8, false>(P.cus, g.ntasks, grid);
+    }
+    hipLaunchKernelGGL((k_pack_batched<NB, false>), dim3((unsigned)g.grid), dim3(256), 0, st,
                        (const BProb*)(P.dmem + g.off_probs), (int)g.members.size());
-    if (CT == 1 && NW == 4) launch_blocked<NB, 1, 4>(g, P.dmem, err, qnext, st);
-    else if (CT == 1 && NW == 8) launch_blocked<NB, 1, 8>(g, P.dmem, err, qnext, st);
-    else if (CT == 2 && NW == 4) launch_blocked<NB, 2, 4>(g, P.dmem, err, qnext, st);
-    else launch_blocked<NB, 2, 8>(g, P.dmem, err, qnext, st);
+    if (CT == 1 && NW == 4) launch_blocked<NB, 1, 4, false>(g, P.dmem, err, qnext, st);
+    else if (CT == 1 && NW == 8) launch_blocked<NB, 1, 8, false>(g, P.dmem, err, qnext, st);
+    else if (CT == 2 && NW == 4) launch_blocked<NB, 2, 4, false>(g, P.dmem, err, qnext, st);
+    else launch_blocked<NB, 2, 8, false>(g, P.dmem, err, qnext, st);
     return TRBT_SUCCESS;
 }
 
@@ -232,9 +246,16 @@ int dispatch_group(const trbt_plan& P, const Group& g, int gi, hipStream_t st, b
     unsigned* err = (unsigned*)P.dmem;
     int* qnext = (int*)(P.dmem + 256) + gi * NXCD * QSTRIDE;
     if (!g.blocked) {
-        if (!grid_only)
-            hipLaunchKernelGGL(k_unblocked_batched, dim3((unsigned)g.grid), dim3(64), 0, st,
-                               (const BProb*)(P.dmem + g.off_probs), (int)g.members.size());
+        if (!grid_only) {
+            if (P.cplx)
+                hipLaunchKernelGGL(k_unblocked_batched<cd>, dim3((unsigned)g.grid), dim3(64), 0,
+                                   st, (const BProb*)(P.dmem + g.off_probs),
+                                   (int)g.members.size());
+            else
+                hipLaunchKernelGGL(k_unblocked_batched<double>, dim3((unsigned)g.grid),
+                                   dim3(64), 0, st, (const BProb*)(P.dmem + g.off_probs),
+                                   (int)g.members.size());
+        }
         return TRBT_SUCCESS;
     }
     switch (g.nbw) {
@@ -262,7 +283,7 @@ int build_tables(trbt_plan& P, const std::vector<double*>& zptr)
         for (int i = 0; i < count; ++i) {
             const trbt_problem_d& p = P.probs[i];
             if (num_reflectors(p.n, p.nbw) == 0 || p.nev == 0) continue;
-            const bool elig = use_blocked(p.n, p.nbw, false) && !stream_all;
+            const bool elig = use_blocked(p.n, p.nbw, P.cplx) && !stream_all;
             if (g.blocked ? (elig && p.nbw == g.nbw) : (gi == 4 && !elig)) g.members.push_back(i);
         }
         if (!g.members.empty()) P.groups.push_back(g);
@@ -280,7 +301,7 @@ int build_tables(trbt_plan& P, const std::vector<double*>& zptr)
         Group& g = P.groups[gi];
         // largest problems first: their strips start first
         std::stable_sort(g.members.begin(), g.members.end(), [&](int a, int b) {
-            return problem_cost(P.probs[a]) > problem_cost(P.probs[b]);
+            return problem_cost(P.probs[a], P.cplx) > problem_cost(P.probs[b], P.cplx);
         });
         const int np = (int)g.members.size();
         std::vector<BProb> bp(np);
@@ -310,7 +331,7 @@ int build_tables(trbt_plan& P, const std::vector<double*>& zptr)
             for (int m = 0; m < np; ++m) order[m] = m;
             auto total = [&](int m) {
                 const trbt_problem_d& p = P.probs[g.members[m]];
-                return problem_cost(p) * ((p.nev + cols - 1) / cols);
+                return problem_cost(p, P.cplx) * ((p.nev + cols - 1) / cols);
             };
             std::stable_sort(order.begin(), order.end(),
                              [&](int a, int b) { return total(a) > total(b); });
@@ -324,8 +345,8 @@ int build_tables(trbt_plan& P, const std::vector<double*>& zptr)
             for (int x = 0; x < NXCD; ++x) {
                 qbegin[x] = (int)tasks.size();
                 std::stable_sort(q[x].begin(), q[x].end(), [&](int a, int b) {
-                    return problem_cost(P.probs[g.members[a]]) >
-                           problem_cost(P.probs[g.members[b]]);
+                    return problem_cost(P.probs[g.members[a]], P.cplx) >
+                           problem_cost(P.probs[g.members[b]], P.cplx);
                 });
                 for (int m : q[x]) {
                     const int64_t strips = (P.probs[g.members[m]].nev + cols - 1) / cols;
@@ -441,7 +462,8 @@ int tune(trbt_plan& P)
     for (size_t i = 0; i < P.probs.size(); ++i) {
         const trbt_problem_d& p = P.probs[i];
         zoff[i] = zbytes;
-        if (p.nev > 0 && p.n > 0) zlen[i] = ((size_t)(p.nev - 1) * p.ldz + p.n) * sizeof(double);
+        if (p.nev > 0 && p.n > 0)
+            zlen[i] = ((size_t)(p.nev - 1) * p.ldz + p.n) * sizeof(double) * (P.cplx ? 2 : 1);
         zbytes = align_up(zbytes + zlen[i], 256);
     }
     char* scratch = nullptr;
@@ -461,13 +483,14 @@ int tune(trbt_plan& P)
     int64_t max_n = 0;
     for (const trbt_problem_d& p : P.probs) {
         const bool active = num_reflectors(p.n, p.nbw) > 0 && p.nev > 0;
-        any_blocked |= active && use_blocked(p.n, p.nbw, false);
+        any_blocked |= active && use_blocked(p.n, p.nbw, P.cplx);
         if (active) max_n = std::max(max_n, p.n);
     }
     std::vector<trbt_plan_config> cands;
     if (any_blocked) {
         for (int cols : {16, 32})
-            for (int waves : {8, 4}) cands.push_back({cols, waves, 16});
+            for (int waves : {8, 4})
+                if (cols == 16 || !P.cplx) cands.push_back({cols, waves, 16});
     }
     // The streaming form (one lane per column, a dependent chain of K
     // reflectors per lane) only competes on tiny problems; beyond that a
@@ -494,15 +517,14 @@ int tune(trbt_plan& P)
     return rc;
 }
 
-}  // namespace
-
-extern "C" {
-
-int trbt_plan_create_batched_d(const trbt_problem_d* probs, int count,
-                               const trbt_plan_config* cfg, trbt_plan** plan, void* stream)
+// Plan creation for real (cplx = false) or complex problems, given as
+// real-typed descriptors (complex pointers reinterpreted as interleaved
+// doubles).
+int create_plan(const trbt_problem_d* probs, int count, bool cplx,
+                const trbt_plan_config* cfg, trbt_plan** plan, void* stream)
 {
     if (count < 0 || (count > 0 && !probs)) return count < 0 ? -2 : -1;
-    if (cfg && !valid_config(*cfg)) return -3;
+    if (cfg && !valid_config(*cfg, cplx)) return -3;
     if (!plan) return -4;
     *plan = nullptr;
     for (int i = 0; i < count; ++i) {
@@ -515,6 +537,7 @@ int trbt_plan_create_batched_d(const trbt_problem_d* probs, int count,
 
     trbt_plan* P = new (std::nothrow) trbt_plan;
     if (!P) return TRBT_ERR_HIP;
+    P->cplx = cplx;
     P->probs.assign(probs, probs + count);
     hipDeviceProp_t prop;
     if (hipGetDevice(&P->device) != hipSuccess ||
@@ -532,10 +555,10 @@ int trbt_plan_create_batched_d(const trbt_problem_d* probs, int count,
     for (int i = 0; i < count; ++i) {
         const trbt_problem_d& p = probs[i];
         const bool active = num_reflectors(p.n, p.nbw) > 0 && p.nev > 0;
-        if (active && use_blocked(p.n, p.nbw, false)) {
+        if (active && use_blocked(p.n, p.nbw, cplx)) {
             off = align_up(off, 256);
             P->ws_off[i] = off;
-            off += blocked_bytes(p.n, p.nbw, false) - HDR_BYTES;
+            off += blocked_bytes(p.n, p.nbw, cplx) - HDR_BYTES;
         }
         tables += sizeof(BProb) + sizeof(BTask) * (size_t)((p.nev + 15) / 16);
     }
@@ -575,6 +598,29 @@ int trbt_plan_create_batched_d(const trbt_problem_d* probs, int count,
     }
     *plan = P;
     return TRBT_SUCCESS;
+}
+
+}  // namespace
+
+extern "C" {
+
+int trbt_plan_create_batched_d(const trbt_problem_d* probs, int count,
+                               const trbt_plan_config* cfg, trbt_plan** plan, void* stream)
+{
+    return create_plan(probs, count, false, cfg, plan, stream);
+}
+
+int trbt_plan_create_batched_z(const trbt_problem_z* probs, int count,
+                               const trbt_plan_config* cfg, trbt_plan** plan, void* stream)
+{
+    if (count < 0 || (count > 0 && !probs)) return count < 0 ? -2 : -1;
+    std::vector<trbt_problem_d> d(count > 0 ? count : 0);
+    for (int i = 0; i < count; ++i) {
+        const trbt_problem_z& p = probs[i];
+        d[i] = trbt_problem_d{p.n, p.nbw, p.nev, (const double*)p.hh_v, (const double*)p.hh_tau,
+                              (double*)p.Z, p.ldz};
+    }
+    return create_plan(d.data(), count, true, cfg, plan, stream);
 }
 
 int trbt_plan_exec(trbt_plan* plan, void* stream)

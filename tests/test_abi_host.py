@@ -158,6 +158,26 @@ def test_plan_validation_codes(T):
     assert lib.trbt_plan_destroy(None) == 0
 
 
+def test_complex_plan_validation_codes(T):
+    """Complex plans: the same host-side checks, and 32-column strips are
+    not a complex configuration (-3)."""
+    import ctypes as C
+    lib = T.lib()
+    good = T.trbt_problem_z(100, 32, 10, FAKE, FAKE, FAKE, 100)
+    arr = (T.trbt_problem_z * 2)(good, good)
+    h = C.c_void_p()
+    assert lib.trbt_plan_create_batched_z(None, 2, None, C.byref(h), None) == -1
+    assert lib.trbt_plan_create_batched_z(arr, -1, None, C.byref(h), None) == -2
+    for bad in [(32, 8, 16), (32, 4, 1), (16, 6, 16)]:
+        cfg = T.trbt_plan_config(*bad)
+        assert lib.trbt_plan_create_batched_z(arr, 2, C.byref(cfg), C.byref(h), None) == -3
+    assert lib.trbt_plan_create_batched_z(arr, 2, None, None, None) == -4
+    bad = T.trbt_problem_z(100, 32, 10, FAKE, FAKE, FAKE, 50)   # ldz < n
+    arr2 = (T.trbt_problem_z * 2)(good, bad)
+    assert lib.trbt_plan_create_batched_z(arr2, 2, None, C.byref(h), None) == -1001
+    assert h.value is None
+
+
 def test_adjoint_validation_codes(T):
     """The adjoint entry point checks its 15 arguments on the host, in order,
     before any HIP call."""

@@ -32,27 +32,28 @@ def _torch():
     return torch
 
 
-def _problem_inputs(n, nbw, nev, seed, oracle_mod):
+def _problem_inputs(n, nbw, nev, seed, oracle_mod, dt="d"):
     import synth
     lengths = oracle_mod.reflector_table(n, nbw)[3] if n >= 3 and nbw >= 2 else np.zeros(0, np.int64)
-    V, tau = synth.unitary_reflectors(lengths, nbw, seed, "d")
-    Z = synth.gaussian(n, nev, seed + 1, "d") if nev else np.zeros((n, 0))
+    V, tau = synth.unitary_reflectors(lengths, nbw, seed, dt)
+    Z = synth.gaussian(n, nev, seed + 1, dt) if nev else np.zeros((n, 0), V.dtype)
     return Z, V, tau
 
 
 class DeviceBatch:
     """Device buffers of a batch: Z (nev, ldz) per problem, hh_v, hh_tau."""
 
-    def __init__(self, shapes, pad=0):
+    def __init__(self, shapes, pad=0, cplx=False):
         torch = _torch()
+        dtype = torch.complex128 if cplx else torch.float64
         self.shapes = shapes
         self.Z, self.V, self.tau = [], [], []
         for n, nbw, nev in shapes:
             K = max(int(_K(n, nbw)), 1)
             ldz = max(n, 1) + pad
-            self.Z.append(torch.zeros(max(nev, 1), ldz, dtype=torch.float64, device="cuda"))
-            self.V.append(torch.zeros(K, nbw, dtype=torch.float64, device="cuda"))
-            self.tau.append(torch.zeros(K, dtype=torch.float64, device="cuda"))
+            self.Z.append(torch.zeros(max(nev, 1), ldz, dtype=dtype, device="cuda"))
+            self.V.append(torch.zeros(K, nbw, dtype=dtype, device="cuda"))
+            self.tau.append(torch.zeros(K, dtype=dtype, device="cuda"))
 
     def load(self, inputs):
         torch = _torch()
@@ -260,3 +261,76 @@ def test_c4_pipeline_problems(oracle_mod):
         n = B.shape[0]
         assert np.linalg.norm(B @ Y - Y * p["w"]) / np.linalg.norm(B) <= 1e-12 * n
         assert np.linalg.norm(Y.T @ Y - np.eye(Y.shape[1])) <= 1e-12 * n
+
+
+# complex Hermitian problems: blocked groups for every nbw, the streaming form,
+# ragged nev and problems with nothing to do
+CMIXED = [
+    (300, 32, 150), (97, 32, 33), (200, 16, 17), (150, 48, 65), (301, 64, 63),
+    (90, 64, 1), (129, 24, 31), (61, 3, 20), (2, 32, 2), (64, 32, 0),
+]
+
+
+@pytest.mark.parametrize("cfg", [(16, 8, 16), (16, 4, 16), (16, 8, 1), None],
+                         ids=lambda c: "tuned" if c is None else "x".join(map(str, c)))
+def test_batched_complex_two_replays(oracle_mod, cfg):
+    import paper_2002_10991_amd as T
+    print(f"[gpu] batched complex cfg={cfg}", flush=True)
+    batch = DeviceBatch(CMIXED, pad=2, cplx=True)
+    inputs = [_problem_inputs(n, nbw, nev, 700 + 3 * i, oracle_mod, "z")
+              for i, (n, nbw, nev) in enumerate(CMIXED)]
+    batch.load(inputs)
+    plan = T.BatchedPlan(batch.problems(), cfg)
+    try:
+        got_cfg, ms = plan.config
+        if cfg is not None:
+            assert got_cfg == tuple(cfg) and ms == 0.0
+        else:
+            assert got_cfg[0] == 16 and ms > 0.0
+        for rep, seed0 in enumerate((700, 1100)):
+            if rep:
+                inputs = [_problem_inputs(n, nbw, nev, seed0 + 3 * i, oracle_mod, "z")
+                          for i, (n, nbw, nev) in enumerate(CMIXED)]
+                batch.load(inputs)
+            plan.run()
+            _torch().cuda.synchronize()
+            assert plan.fault() == 0
+            _check_against_oracle(batch, inputs, oracle_mod)
+    finally:
+        plan.close()
+
+
+@pytest.mark.parametrize("cfg", [(16, 8, 16), (16, 4, 16)], ids=lambda c: "x".join(map(str, c)))
+def test_batched_complex_equals_looped_bitwise(oracle_mod, cfg):
+    """Complex plans run the single-call per-column arithmetic too: results
+    agree bitwise with looped trans_ev_tridi_to_band_z calls."""
+    import paper_2002_10991_amd as T
+    torch = _torch()
+    shapes = [(300, 32, 150), (97, 32, 33), (200, 16, 17), (150, 48, 65), (129, 24, 31),
+              (260, 64, 40)]
+    inputs = [_problem_inputs(n, nbw, nev, 80 + i, oracle_mod, "z")
+              for i, (n, nbw, nev) in enumerate(shapes)]
+    a, b = DeviceBatch(shapes, cplx=True), DeviceBatch(shapes, cplx=True)
+    a.load(inputs)
+    b.load(inputs)
+    plan = T.BatchedPlan(a.problems(), cfg)
+    plan.run()
+    for Zv, V, tau, nbw in b.problems():
+        T.back_transform(Zv, V, tau, nbw)
+    torch.cuda.synchronize()
+    plan.close()
+    for i in range(len(shapes)):
+        assert np.array_equal(a.result(i), b.result(i)), (i, shapes[i])
+
+
+def test_batched_rejects_mixed_precision():
+    import paper_2002_10991_amd as T
+    torch = _torch()
+    Zr = torch.zeros(4, 100, dtype=torch.float64, device="cuda")
+    Zc = torch.zeros(4, 100, dtype=torch.complex128, device="cuda")
+    Vr = torch.zeros(10, 8, dtype=torch.float64, device="cuda")
+    Vc = torch.zeros(10, 8, dtype=torch.complex128, device="cuda")
+    tr = torch.zeros(10, dtype=torch.float64, device="cuda")
+    tc = torch.zeros(10, dtype=torch.complex128, device="cuda")
+    with pytest.raises(TypeError):
+        T.BatchedPlan([(Zr.T, Vr, tr, 8), (Zc.T, Vc, tc, 8)])
