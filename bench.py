@@ -80,52 +80,56 @@ def cpu_baseline(cfg, V, tau, Z, L_total, budget_s=20.0):
                       f"{dt:.1f} s wall; rate scales to all columns (columns are independent)"}
 
 
-def c4_inputs():
-    """The batched workload: 64 real problems, n_p = 512*U{1..8} (seed 1004),
-    nbw = 32, nev = n_p/2, per-problem seeds from SeedSequence(1004)."""
+def c4_inputs(dt: str = "d"):
+    """The batched workload: 64 problems, n_p = 512*U{1..8} (seed 1004),
+    nbw = 32, nev = n_p/2, per-problem seeds from SeedSequence(1004); real
+    (dt "d", C4) or complex Hermitian (dt "z", C4z)."""
     import synth
     sizes, seeds = synth.batched_sizes(), synth.batched_seeds()
     out = []
     for n, sd in zip(sizes, seeds):
         n = int(n)
         lengths = synth.reflector_lengths(n, 32)
-        V, tau = synth.unitary_reflectors(lengths, 32, sd, "d")
-        Z = synth.gaussian(n, n // 2, sd + 1, "d")
+        V, tau = synth.unitary_reflectors(lengths, 32, sd, dt)
+        Z = synth.gaussian(n, n // 2, sd + 1, dt)
         out.append((n, 32, n // 2, int(lengths.sum()), V, tau, Z))
     return out
 
 
-def batched_leg(steps: int, warmup: int):
+def batched_leg(steps: int, warmup: int, dt: str = "d"):
     """Batched plan (one persistent graph-captured launch, autotuned) against
     64 looped single-problem calls on one stream, same inputs, same stream."""
     import torch
     import paper_2002_10991_amd as T
     dev = torch.device("cuda:0")
+    cplx = dt == "z"
+    name = "C4z" if cplx else "C4"
     t = time.perf_counter()
-    probs = c4_inputs()
-    log(f"C4 inputs ready in {time.perf_counter() - t:.1f}s")
-    flops = sum(4 * nev * L for n, nbw, nev, L, V, tau, Z in probs)
+    probs = c4_inputs(dt)
+    log(f"{name} inputs ready in {time.perf_counter() - t:.1f}s")
+    flops = sum((16 if cplx else 4) * nev * L for n, nbw, nev, L, V, tau, Z in probs)
     tensors = []
     for n, nbw, nev, L, V, tau, Z in probs:
         tensors.append((torch.from_numpy(np.ascontiguousarray(Z.T)).to(dev),
                         torch.from_numpy(V).to(dev), torch.from_numpy(tau).to(dev), nbw))
     stream = torch.cuda.current_stream()
-    wmax = max(T.trbt_workspace_bytes(n, nbw, nev, False) for n, nbw, nev, *_ in probs)
+    wmax = max(T.trbt_workspace_bytes(n, nbw, nev, cplx) for n, nbw, nev, *_ in probs)
     work = torch.empty(wmax + T.TRBT_WORK_ALIGN, dtype=torch.uint8, device=dev)
     work = work[(-work.data_ptr()) % T.TRBT_WORK_ALIGN:][:wmax]
+    single = T.trans_ev_tridi_to_band_z if cplx else T.trans_ev_tridi_to_band_d
 
     def looped():
         for Zb, Vd, td, nbw in tensors:
             n, nev = Zb.shape[1], Zb.shape[0]
-            rc = T.trans_ev_tridi_to_band_d(n, nbw, nev, Vd, td, Zb, n, work, wmax, stream)
+            rc = single(n, nbw, nev, Vd, td, Zb, n, work, wmax, stream)
             if rc:
-                raise T.TrbtError(rc, "trans_ev_tridi_to_band_d")
+                raise T.TrbtError(rc, single.__name__)
 
     t = time.perf_counter()
     plan = T.BatchedPlan([(Zb.T, Vd, td, nbw) for Zb, Vd, td, nbw in tensors], None, stream)
     create_s = time.perf_counter() - t
     cfg, tuned_ms = plan.config
-    log(f"C4 plan created in {create_s:.2f}s, tuned config {cfg} ({tuned_ms:.3f} ms)")
+    log(f"{name} plan created in {create_s:.2f}s, tuned config {cfg} ({tuned_ms:.3f} ms)")
 
     def timed(fn):
         for _ in range(warmup):
@@ -140,14 +144,15 @@ def batched_leg(steps: int, warmup: int):
         return e0.elapsed_time(e1) / steps
 
     loop_ms = timed(looped)
-    log(f"C4 looped: {loop_ms:.3f} ms per batch")
+    log(f"{name} looped: {loop_ms:.3f} ms per batch")
     batch_ms = timed(plan.run)
-    log(f"C4 batched: {batch_ms:.3f} ms per batch")
+    log(f"{name} batched: {batch_ms:.3f} ms per batch")
     if plan.fault():
         raise RuntimeError("batched plan: device wait-timeout flag set")
     plan.close()
     return {
-        "workload": "C4: 64 real problems, n_p = 512*U{1..8} (seed 1004), nbw=32, nev=n_p/2",
+        "workload": (f"{name}: 64 {'complex Hermitian' if cplx else 'real'} problems, "
+                     "n_p = 512*U{1..8} (seed 1004), nbw=32, nev=n_p/2"),
         "flops_per_batch": flops,
         "batched_ms": round(batch_ms, 4), "looped_ms": round(loop_ms, 4),
         "batched_tflops": round(flops / batch_ms / 1e9, 4),
@@ -366,7 +371,9 @@ def main():
     import paper_2002_10991_amd as T
 
     if args.batched_only:
-        print(json.dumps({"batched_vs_loop": batched_leg(args.steps, args.warmup)}), flush=True)
+        print(json.dumps({"batched_vs_loop": batched_leg(args.steps, args.warmup),
+                          "batched_complex_vs_loop": batched_leg(args.steps, args.warmup, "z")}),
+              flush=True)
         return
     if args.adjoint_only:
         print(json.dumps({"adjoint_vs_plain": adjoint_leg(args.warmup, not args.no_plain)}),
@@ -460,6 +467,7 @@ def main():
     }
     if not args.no_batched:
         out["batched_vs_loop"] = batched_leg(args.steps, args.warmup)
+        out["batched_complex_vs_loop"] = batched_leg(args.steps, args.warmup, "z")
     if not args.no_adjoint:
         out["adjoint_vs_plain"] = adjoint_leg(args.warmup, not args.no_plain)
     if not args.no_cpu_baseline:

@@ -334,3 +334,42 @@ def test_batched_rejects_mixed_precision():
     tc = torch.zeros(10, dtype=torch.complex128, device="cuda")
     with pytest.raises(TypeError):
         T.BatchedPlan([(Zr.T, Vr, tr, 8), (Zc.T, Vc, tc, 8)])
+
+
+def test_c4z_full_batch_sampled(oracle_mod):
+    """The complex batch the benchmark times (64 problems, n_p = 512*U{1..8},
+    nbw=32, nev=n_p/2, same seeds as the real one) with the autotuned plan:
+    every problem checked on sampled columns against the oracle, and in full
+    (bitwise) against looped single complex calls."""
+    import paper_2002_10991_amd as T
+    import synth
+    torch = _torch()
+    shapes = _c4_shapes()
+    seeds = synth.batched_seeds()
+    inputs = []
+    for i, (n, nbw, nev) in enumerate(shapes):
+        lengths = synth.reflector_lengths(n, nbw)
+        V, tau = synth.unitary_reflectors(lengths, nbw, seeds[i], "z")
+        Z = synth.gaussian(n, nev, seeds[i] + 1, "z")
+        inputs.append((Z, V, tau))
+    print(f"[gpu] C4z batch: {len(shapes)} complex problems", flush=True)
+    a, b = DeviceBatch(shapes, cplx=True), DeviceBatch(shapes, cplx=True)
+    a.load(inputs)
+    b.load(inputs)
+    plan = T.BatchedPlan(a.problems(), None)
+    print(f"[gpu] C4z tuned config {plan.config}", flush=True)
+    plan.run()
+    torch.cuda.synchronize()
+    assert plan.fault() == 0
+    plan.close()
+    for Zv, V, tau, nbw in b.problems():
+        T.back_transform(Zv, V, tau, nbw)
+    torch.cuda.synchronize()
+    rng = np.random.default_rng(5)
+    for i, (n, nbw, nev) in enumerate(shapes):
+        out = a.result(i)
+        cols = np.unique(np.concatenate([[0, nev - 1], rng.integers(0, nev, 4)]))
+        Z, V, tau = inputs[i]
+        ref = oracle_mod.back_transform(Z, V, tau, nbw, cols=cols)
+        assert _relerr(out[:, cols], ref) <= TOL, (i, n)
+        assert np.array_equal(out, b.result(i)), (i, n)
