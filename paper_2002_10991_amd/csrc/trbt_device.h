@@ -215,8 +215,16 @@ struct WyBlock {
     double Gm[16][16][NC];
     double Tm[16][16][NC];
     double tau[16][NC];
+    double Gp[4][16][16][NC];   // per-wave partial Gram matrices
     int64_t j, t;
 };
+
+// D + A B on v_mfma_f64_16x16x4_f64 (A lane i+16k = A[i][k], B lane j+16k =
+// B[k][j]; D lane j+16g, element e = D[g+4e][j]).
+__device__ inline d4 pack_mfma(double a, double b, d4 c)
+{
+    return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+}
 
 // wy_factor fills W for block `blk` (slot-major numbering): the reflectors
 // in window layout, their Gram matrix and the forward factor T.  All 256
@@ -273,20 +281,36 @@ __device__ inline void wy_factor(int64_t n, const double* __restrict__ hv,
         if (CPLX) Vt[r][p][NC - 1] = im;
     }
     __syncthreads();
-    {   // Gram matrix Gm[a][b] = sum_r conj(Vt[r][a]) Vt[r][b]
-        const int a = tid / 16, b = tid % 16;
-        double gr = 0.0, gi = 0.0;
-        for (int r = 0; r < R; ++r) {
+    {   // Gram matrix Gm = V^H V on MFMA: K runs over the window rows, wave w
+        // taking the 4-row chunks kc = w (mod 4); the A operand (V^H) and
+        // the B operand (V) of a chunk are the same LDS element per lane
+        // (conjugated for A)
+        const int lane = tid & 63, w = tid >> 6;
+        d4 gr = d4{0.0, 0.0, 0.0, 0.0}, gi = gr;
+        for (int kc = w; kc < R / 4; kc += 4) {
+            const int r = 4 * kc + lane / 16, c = lane % 16;
+            const double vr = Vt[r][c][0];
+            gr = pack_mfma(vr, vr, gr);
             if (CPLX) {
-                cd x = {Vt[r][a][0], Vt[r][a][NC - 1]}, y = {Vt[r][b][0], Vt[r][b][NC - 1]};
-                gr += conj_mul_re(x, y);
-                gi += conj_mul_im(x, y);
-            } else {
-                gr += Vt[r][a][0] * Vt[r][b][0];
+                const double vi = Vt[r][c][NC - 1];
+                gr = pack_mfma(vi, vi, gr);        // Re: vr.vr + vi.vi
+                gi = pack_mfma(vr, vi, gi);        // Im: vr.vi - vi.vr
+                gi = pack_mfma(-vi, vr, gi);
             }
         }
-        Gm[a][b][0] = gr;
-        if (CPLX) Gm[a][b][NC - 1] = gi;
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+            W.Gp[w][lane / 16 + 4 * e][lane % 16][0] = gr[e];
+            if (CPLX) W.Gp[w][lane / 16 + 4 * e][lane % 16][NC - 1] = gi[e];
+        }
+    }
+    __syncthreads();
+    {   // the waves' partials in a fixed order; T starts as diag(tau)
+        const int a = tid / 16, b = tid % 16;
+#pragma unroll
+        for (int k = 0; k < NC; ++k)
+            Gm[a][b][k] = (W.Gp[0][a][b][k] + W.Gp[1][a][b][k]) +
+                          (W.Gp[2][a][b][k] + W.Gp[3][a][b][k]);
         Tm[a][b][0] = (a == b) ? tau[a][0] : 0.0;
         if (CPLX) Tm[a][b][NC - 1] = (a == b) ? tau[a][NC - 1] : 0.0;
     }
@@ -336,27 +360,38 @@ __device__ inline void pack_block(int64_t n, const double* __restrict__ hv,
     // register tile of window tile 0 in this block (the block's position in
     // its slot's sequence is W.t - W.j * NB/16); real windows do not rotate
     const int rot = CPLX ? (int)((NT - (W.t - W.j * (NB / 16)) % NT) % NT) : 0;
-    // A1 chunks and -V chunks
     double* out = ws + (size_t)blk * G::PB;
+    {   // A1 = T V^H, as A1^T = conj(V) T^T on MFMA, one 16-row window tile
+        // q per product (K = the 16 reflectors), wave w taking q = w (mod 4).
+        // Element e of the result in lane l is A1^T[16q + 4e + l/16][l%16] =
+        // A1[l%16][16q + 4e + l/16]: exactly A1 chunk (q, u = e) as the main
+        // kernel reads it.
+        const int lane = tid & 63, w = tid >> 6;
+        for (int q = w; q < NT; q += 4) {
+            const int h = (q + rot) % NT;
+            d4 ar = d4{0.0, 0.0, 0.0, 0.0}, ai = ar;
+#pragma unroll
+            for (int kc = 0; kc < 4; ++kc) {
+                const int r = 16 * q + lane % 16, c = 4 * kc + lane / 16;
+                const double vr = Vt[r][c][0], tr = Tm[lane % 16][c][0];
+                ar = pack_mfma(vr, tr, ar);
+                if (CPLX) {   // (vr - i vi)(tr + i ti)
+                    const double vi = Vt[r][c][NC - 1], ti = Tm[lane % 16][c][NC - 1];
+                    ar = pack_mfma(vi, ti, ar);
+                    ai = pack_mfma(vr, ti, ai);
+                    ai = pack_mfma(-vi, tr, ai);
+                }
+            }
+#pragma unroll
+            for (int e = 0; e < 4; ++e) {
+                out[(4 * h + e) * G::CHUNK + lane] = ar[e];
+                if (CPLX) out[(4 * h + e) * G::CHUNK + 64 + lane] = ai[e];
+            }
+        }
+    }
     for (int idx = tid; idx < NT * 4 * 64; idx += 256) {
         const int lane = idx % 64, qu = idx / 64, q = qu / 4, u = qu % 4;
         const int h = (q + rot) % NT;
-        {   // A1[p][r] = sum_{q' >= p} T[p][q'] conj(Vt[r][q'])
-            const int p = lane % 16, r = 16 * q + 4 * u + lane / 16;
-            double ar = 0.0, ai = 0.0;
-            for (int c = p; c < 16; ++c) {
-                const double tr = Tm[p][c][0], vr = Vt[r][c][0];
-                if (CPLX) {
-                    const double ti = Tm[p][c][NC - 1], vi = -Vt[r][c][NC - 1];
-                    ar += tr * vr - ti * vi;
-                    ai += tr * vi + ti * vr;
-                } else {
-                    ar += tr * vr;
-                }
-            }
-            out[(4 * h + u) * G::CHUNK + lane] = ar;
-            if (CPLX) out[(4 * h + u) * G::CHUNK + 64 + lane] = ai;
-        }
         {   // -V chunks in the order the main kernel reads them.  Real: u
             // ascending, and within each u the tiles from the bottom of the
             // window up.  Complex: tile by tile from the bottom up, u
