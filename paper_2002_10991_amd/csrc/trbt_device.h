@@ -211,12 +211,14 @@ struct Geo {
 template <int NB, bool CPLX>
 struct WyBlock {
     static constexpr int NT = Geo<NB, CPLX>::NT, NC = Geo<NB, CPLX>::NC, R = 16 * NT;
-    double Vt[R][16][NC];
+    double Vt[R][17][NC];       // (one column of padding: the V load writes down columns)
     double Gm[16][16][NC];
     double Tm[16][16][NC];
     double tau[16][NC];
     double Gp[4][16][16][NC];   // per-wave partial Gram matrices
     int64_t j, t;
+    int64_t kref[16];           // reflector index of position p (-1: none)
+    int lref[16];               // its length
 };
 
 // D + A B on v_mfma_f64_16x16x4_f64 (A lane i+16k = A[i][k], B lane j+16k =
@@ -256,26 +258,35 @@ __device__ inline void wy_factor(int64_t n, const double* __restrict__ hv,
     const int64_t j = W.j, t = W.t;
     const int64_t s_top = n - 3 - KB * t;
 
-    for (int idx = tid; idx < R * 16; idx += 256) {
-        const int r = idx / 16, p = idx % 16;
+    if (tid < 16) {   // the block's reflector in position p, its length and tau
+        const int p = tid;
         const int64_t s = s_top - 15 + p;
-        double re = 0.0, im = 0.0;
+        int64_t k = -1;
+        int len = 0;
+        double tr = 0.0, ti = 0.0;
         if (s >= 0 && s <= n - 3 - j * NB) {
-            const int64_t k = stage_offset(n, NB, s) + j;
+            k = stage_offset(n, NB, s) + j;
             const int64_t r0 = s + 1 + j * NB;
-            const int len = (int)(n - r0 < NB ? n - r0 : NB);
-            const int e = r - (p + 1);
-            if (e >= 0 && e < len) {
-                re = hv[(k * NB + e) * NC];
-                if (CPLX) im = hv[(k * NB + e) * NC + 1];
-            }
-            if (r == 0) {
-                tau[p][0] = ht[k * NC];
-                if (CPLX) tau[p][NC - 1] = ht[k * NC + 1];
-            }
-        } else if (r == 0) {
-            tau[p][0] = 0.0;
-            if (CPLX) tau[p][NC - 1] = 0.0;
+            len = (int)(n - r0 < NB ? n - r0 : NB);
+            tr = ht[k * NC];
+            if (CPLX) ti = ht[k * NC + 1];
+        }
+        W.kref[p] = k;
+        W.lref[p] = len;
+        tau[p][0] = tr;
+        if (CPLX) tau[p][NC - 1] = ti;
+    }
+    __syncthreads();
+    // reflector by reflector, so that consecutive threads read consecutive
+    // elements of one reflector
+    for (int idx = tid; idx < R * 16; idx += 256) {
+        const int p = idx / R, r = idx % R;
+        const int64_t k = W.kref[p];
+        const int e = r - (p + 1);
+        double re = 0.0, im = 0.0;
+        if (k >= 0 && e >= 0 && e < W.lref[p]) {
+            re = hv[(k * NB + e) * NC];
+            if (CPLX) im = hv[(k * NB + e) * NC + 1];
         }
         Vt[r][p][0] = re;
         if (CPLX) Vt[r][p][NC - 1] = im;
