@@ -747,18 +747,6 @@ __device__ __attribute__((always_inline)) inline void blocked_strip(int64_t n, i
         for (int64_t t = t0; t < nblk; ++t, boff += G::PB * sizeof(double), p0 -= KB) {
             const bool has_next = t + 1 < nblk;
             const int ret = rot == 0 ? NT - 1 : rot - 1;   // register tile of the bottom tile
-            if constexpr (CKPT) {
-                double* cp = ckpt + ((size_t)(slot_base(j, nblk, nt1) + t - t0) * NT * nstrips +
-                                     strip) * 256 + lane;
-#pragma unroll
-                for (int h = 0; h < NT; ++h) {
-                    const int q = h >= rot ? h - rot : h + NT - rot;
-#pragma unroll
-                    for (int e = 0; e < 4; ++e)
-                        __builtin_nontemporal_store(zt[h][0].re[e],
-                                                    &cp[(size_t)q * nstrips * 256 + e * 64]);
-                }
-            }
             // the top tile of the next block: slot j-1 must have retired it.
             // From wave w-1's exchange ring when it put it there (slot j-1 is
             // in the same round and this is not the tile of its last block),
@@ -886,6 +874,22 @@ __device__ __attribute__((always_inline)) inline void blocked_strip(int64_t n, i
                 for (int c = 0; c < NCH; ++c) {
                     const double ar = ring_re[c % D];
                     refill(c);
+                    if constexpr (CKPT) {
+                        // the block's input window: GEMM1 has only read it and
+                        // GEMM2 is about to overwrite it (storing here rather
+                        // than at the top of the block keeps the stores out of
+                        // the way of the next tile's wait and load)
+                        if (c == 4 * NT) {
+                            double* cp = ckpt + ((size_t)(slot_base(j, nblk, nt1) + t - t0) * NT *
+                                                 nstrips + strip) * 256 + lane;
+#pragma unroll
+                            for (int q = 0; q < NT; ++q)
+#pragma unroll
+                                for (int e = 0; e < 4; ++e)
+                                    __builtin_nontemporal_store(
+                                        zt[q][0].re[e], &cp[(size_t)q * nstrips * 256 + e * 64]);
+                        }
+                    }
                     if (c < 4 * NT) {
                         // Y += A1(:, chunk) * Zwin(chunk, :)
                         const int h = c / 4, u = c % 4, hp = h & 1;
