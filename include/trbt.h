@@ -290,6 +290,55 @@ int trbt_plan_check(trbt_plan *plan, int *fault);
 /* Free the plan (synchronizes the device first).  NULL is accepted. */
 int trbt_plan_destroy(trbt_plan *plan);
 
+/* ------------------------------------------------------------------------
+ * Banded-to-tridiagonal reduction (the producer of hh_v / hh_tau)
+ *
+ * Bulge chasing, Sec. 2.2.1, Eq. 2stage_fwd2, with reflectors built as in
+ * Eq. householder: for stage s = 0 .. n-3 and sweep j = 0 .. S_s-1, the
+ * reflector H = I - tau v v^H with v[0] = 1 and H^H x = beta e1 (beta real,
+ * beta = -sign(Re x0) ||x||, tau = 0 and v = e1 when x has nothing to
+ * annihilate) is built from column c of the current matrix on rows
+ * [r0, r0+len) (c = s for j = 0, else c = r0 - nbw: the first column of the
+ * bulge left by sweep j-1), and B <- H^H B H.  The reflectors come out in
+ * generation order, exactly the layout trans_ev_tridi_to_band_{d,z} take,
+ * so that  B = Q T Q^H  with Q^* = H_0 H_1 ... H_{K-1} as above.
+ *
+ * Stages run as a pipeline on the GPU: stage s takes sweep j once stage s-1
+ * has finished sweep j+2; the result equals the sequential order's up to
+ * rounding (the same operations on the same data; only the summation order
+ * inside a step differs).
+ * ------------------------------------------------------------------------ */
+
+/* Bytes of device workspace trbt_band_to_tridi_{d,z} need: the band with
+ * 2*nbw stored diagonals (the chase's fill) and one progress counter per
+ * stage.  Errors: -1 n < 0, -2 nbw outside [1, 64], -4 null `bytes`. */
+int trbt_band_to_tridi_workspace_bytes(int64_t n, int nbw, int is_complex, size_t *bytes);
+
+/* Reduce the Hermitian band matrix B (n x n, semi-bandwidth nbw) to the
+ * real symmetric tridiagonal T = diag(d) + subdiag(e) (complex case: e is
+ * complex; after the last stage only e[n-2] keeps a nonzero imaginary part),
+ * writing the reflectors.
+ * Arguments: 1 n >= 0, 2 nbw in [1, 64], 3 ab (device, read-only): B in
+ * LAPACK lower band layout, ab[d + k*ldab] = B(k+d, k) for d = 0..nbw
+ * (entries with k+d >= n ignored; imaginary parts of the diagonal ignored
+ * in the complex case), 4 ldab >= nbw+1, 5 d (device, n reals, out),
+ * 6 e (device, n-1 entries, out), 7 hh_v (device, K x nbw, out; entries at
+ * positions >= len_k written as zero), 8 hh_tau (device, K, out), 9 work
+ * (device, aligned to TRBT_WORK_ALIGN), 10 work_bytes (at least
+ * trbt_band_to_tridi_workspace_bytes), 11 stream.  K =
+ * trbt_num_reflectors(n, nbw); hh_v / hh_tau may be NULL when K == 0 (n < 3
+ * or nbw == 1: the band is already tridiagonal and only d, e are written).
+ * Asynchronous on `stream`, no allocation; TRBT_ERR_WORKSPACE when work is
+ * missing or too small.  Successive calls on one workspace must be ordered
+ * (one stream is enough).  If a pipeline wait ever timed out (never
+ * expected; a 10 s bound per wait), d is filled with NaN. */
+int trbt_band_to_tridi_d(int64_t n, int nbw, const double *ab, int64_t ldab, double *d,
+                         double *e, double *hh_v, double *hh_tau, void *work,
+                         size_t work_bytes, void *stream);
+int trbt_band_to_tridi_z(int64_t n, int nbw, const trbt_z *ab, int64_t ldab, double *d,
+                         trbt_z *e, trbt_z *hh_v, trbt_z *hh_tau, void *work,
+                         size_t work_bytes, void *stream);
+
 /* Static description of a status code (never NULL). */
 const char *trbt_strerror(int status);
 

@@ -25,6 +25,8 @@ __all__ = [
     "trbt_plan_get_config", "trbt_plan_check", "trbt_plan_destroy", "BatchedPlan", "trbt_adjoint_workspace_bytes_d",
     "trans_ev_tridi_to_band_adjoint_d", "trans_ev_tridi_to_band_fwd_ckpt_d",
     "trans_ev_tridi_to_band_bwd_ckpt_d", "adjoint", "BackTransform", "back_transform_autograd",
+    "trbt_band_to_tridi_workspace_bytes", "trbt_band_to_tridi_d", "trbt_band_to_tridi_z",
+    "band_to_tridiagonal",
 ]
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
@@ -87,6 +89,11 @@ def lib():
         L.trans_ev_tridi_to_band_bwd_ckpt_d.argtypes = [i64, i32, i64, vp, vp, vp, i64, vp, vp,
                                                         i32, vp, sz, vp]
         L.trans_ev_tridi_to_band_bwd_ckpt_d.restype = i32
+        L.trbt_band_to_tridi_workspace_bytes.argtypes = [i64, i32, i32, C.POINTER(sz)]
+        L.trbt_band_to_tridi_workspace_bytes.restype = i32
+        for f in (L.trbt_band_to_tridi_d, L.trbt_band_to_tridi_z):
+            f.argtypes = [i64, i32, vp, i64, vp, vp, vp, vp, vp, sz, vp]
+            f.restype = i32
         L.trbt_plan_create_batched_d.argtypes = [C.POINTER(trbt_problem_d), i32,
                                                  C.POINTER(trbt_plan_config),
                                                  C.POINTER(vp), vp]
@@ -484,3 +491,62 @@ def __getattr__(name):
             _Lazy.fn = _back_transform_function()
         return _Lazy.fn
     raise AttributeError(name)
+
+
+# --------------------------------------------------------------------------
+# Banded -> tridiagonal bulge chasing (the producer of hh_v / hh_tau)
+# --------------------------------------------------------------------------
+def trbt_band_to_tridi_workspace_bytes(n: int, nbw: int, is_complex: bool) -> int:
+    nb = C.c_size_t()
+    rc = lib().trbt_band_to_tridi_workspace_bytes(n, nbw, int(bool(is_complex)), C.byref(nb))
+    if rc:
+        raise TrbtError(rc, "trbt_band_to_tridi_workspace_bytes")
+    return nb.value
+
+
+def trbt_band_to_tridi_d(n, nbw, ab, ldab, d, e, hh_v, hh_tau, work, work_bytes,
+                         stream=None) -> int:
+    return lib().trbt_band_to_tridi_d(n, nbw, _ptr(ab), ldab, _ptr(d), _ptr(e), _ptr(hh_v),
+                                      _ptr(hh_tau), _ptr(work), work_bytes, _stream(stream))
+
+
+def trbt_band_to_tridi_z(n, nbw, ab, ldab, d, e, hh_v, hh_tau, work, work_bytes,
+                         stream=None) -> int:
+    return lib().trbt_band_to_tridi_z(n, nbw, _ptr(ab), ldab, _ptr(d), _ptr(e), _ptr(hh_v),
+                                      _ptr(hh_tau), _ptr(work), work_bytes, _stream(stream))
+
+
+def band_to_tridiagonal(ab, nbw: int, work=None, stream=None):
+    """Bulge-chase a Hermitian band matrix to tridiagonal form on the GPU.
+
+    ab: (n, ldab) float64 or complex128 device tensor, C-contiguous, with
+    ab[k, d] = B(k+d, k) for d = 0..nbw (LAPACK lower band storage read
+    column by column).  Returns (d, e, hh_v, hh_tau): d (n,) float64, e
+    (n-1,) of ab's dtype, hh_v (K, nbw) and hh_tau (K,) of ab's dtype, in
+    the generation order trans_ev_tridi_to_band_{d,z} take."""
+    import torch
+    if ab.dim() != 2 or not ab.is_contiguous():
+        raise ValueError("ab must be a contiguous (n, ldab) tensor")
+    n, ldab = ab.shape
+    cplx = ab.dtype == torch.complex128
+    if not cplx and ab.dtype != torch.float64:
+        raise TypeError("ab must be float64 or complex128")
+    K = trbt_num_reflectors(n, nbw)
+    dev = ab.device
+    d = torch.empty(n, dtype=torch.float64, device=dev)
+    e = torch.empty(max(n - 1, 0), dtype=ab.dtype, device=dev)
+    hv = torch.empty((K, nbw), dtype=ab.dtype, device=dev)
+    ht = torch.empty(K, dtype=ab.dtype, device=dev)
+    if work is None:
+        nb = trbt_band_to_tridi_workspace_bytes(n, nbw, cplx)
+        if nb:
+            buf = torch.empty(nb + TRBT_WORK_ALIGN, dtype=torch.uint8, device=dev)
+            off = (-buf.data_ptr()) % TRBT_WORK_ALIGN
+            work = buf[off: off + nb]
+    wb = 0 if work is None else work.numel() * work.element_size()
+    f = trbt_band_to_tridi_z if cplx else trbt_band_to_tridi_d
+    rc = f(n, nbw, ab, ldab, d, e if n > 1 else None, hv if K else None, ht if K else None,
+           work, wb, stream)
+    if rc:
+        raise TrbtError(rc, f.__name__)
+    return d, e, hv, ht

@@ -257,3 +257,43 @@ def test_split_adjoint_validation_codes(T):
     assert callb(ck=1) == -10
     assert callb(work=None, wb=8) == -11
     assert callb(nbw=1, hv=None, ht=None, dv=None, dt=None) == 0
+
+
+@pytest.mark.parametrize("fn", ["trbt_band_to_tridi_d", "trbt_band_to_tridi_z"])
+def test_band_to_tridi_validation_codes(T, fn):
+    f = getattr(T, fn)
+    ok = dict(n=100, nbw=32, ab=FAKE, ldab=33, d=FAKE, e=FAKE, hh_v=FAKE, hh_tau=FAKE,
+              work=None, work_bytes=0)
+
+    def call(**kw):
+        a = dict(ok, **kw)
+        return f(a["n"], a["nbw"], a["ab"], a["ldab"], a["d"], a["e"], a["hh_v"], a["hh_tau"],
+                 a["work"], a["work_bytes"], 0)
+
+    assert call(n=-1) == -1
+    assert call(nbw=0) == -2
+    assert call(nbw=65) == -2          # the chase keeps one block column per lane
+    assert call(ab=None) == -3
+    assert call(ldab=32) == -4
+    assert call(d=None) == -5
+    assert call(e=None) == -6
+    assert call(hh_v=None) == -7
+    assert call(hh_tau=None) == -8
+    assert call(work=FAKE + 8, work_bytes=1 << 20) == -9
+    assert call() == -101                              # TRBT_ERR_WORKSPACE: none given
+    assert call(work=FAKE, work_bytes=1024) == -101    # too small
+    # nothing to annihilate: no reflector buffers needed; n = 0 returns at once
+    assert call(n=0, ab=None, d=None, e=None, hh_v=None, hh_tau=None) == 0
+    assert call(n=50, nbw=1, ldab=2, hh_v=None, hh_tau=None) == -101   # only the workspace missing
+
+
+@pytest.mark.parametrize("n,nbw", [(1, 1), (17, 4), (1000, 64), (32768, 64)])
+def test_band_to_tridi_workspace_formula(T, n, nbw):
+    # header (ticket, error flag), one int progress counter per stage rounded
+    # to 256 bytes, the band with 2*nbw stored diagonals
+    for cplx, elem in ((False, 8), (True, 16)):
+        want = 256 + (4 * n + 255) // 256 * 256 + n * 2 * nbw * elem
+        assert T.trbt_band_to_tridi_workspace_bytes(n, nbw, cplx) == want
+    assert T.trbt_band_to_tridi_workspace_bytes(0, 4, False) == 0
+    with pytest.raises(T.TrbtError):
+        T.trbt_band_to_tridi_workspace_bytes(10, 65, False)
