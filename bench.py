@@ -311,6 +311,93 @@ def adjoint_leg(warmup: int, plain: bool = True):
     return out
 
 
+def chase_flops(n: int, b: int, cplx: bool) -> float:
+    """Algorithmic FP64 flops of the bulge chase: per step, the reflector
+    (~3 len), the left-block update (4 len per column), p = A v and the
+    rank-2 update of the Hermitian diagonal block (4 len^2) and the right
+    block's M v and rank-1 update (4 len nr); complex arithmetic x4."""
+    tot = 0.0
+    for s in range(n - 2):
+        S = (n - s - 2 + b - 1) // b if b > 1 else 0
+        r0 = s + 1 + b * np.arange(S, dtype=np.float64)
+        ln = np.minimum(b, n - r0)
+        nr = np.clip(n - r0 - ln, 0, b)
+        nl = np.where(np.arange(S) == 0, 0, b - 1)
+        tot += float(np.sum(3 * ln + 4 * ln * nl + 4 * ln * ln + 4 * ln * nr))
+    return tot * (4 if cplx else 1)
+
+
+def chase_leg(steps: int, warmup: int, cpu: bool = True):
+    """Banded-to-tridiagonal bulge chasing on the GPU (the producer of the
+    reflectors) on the bands of the n = 32768 complex and n = 8192 real
+    workloads; the oracle's sequential chase timed on an n = 2048 sample of
+    the same bandwidth and scaled by the flop count."""
+    import torch
+    import synth
+    import paper_2002_10991_amd as T
+    dev = torch.device("cuda:0")
+    stream = torch.cuda.current_stream()
+    res = {}
+    for label, n, b, dt, seed, shift in (("C3 band", 32768, 64, "z", 1003, False),
+                                         ("C2 band", 8192, 64, "d", 1002, True)):
+        cplx = dt == "z"
+        tdt = torch.complex128 if cplx else torch.float64
+        ab = synth.band_matrix(n, b, seed, dt, diag_shift=shift)
+        abd = torch.from_numpy(np.ascontiguousarray(ab.T)).to(dev)
+        K = T.trbt_num_reflectors(n, b)
+        d = torch.empty(n, dtype=torch.float64, device=dev)
+        e = torch.empty(n - 1, dtype=tdt, device=dev)
+        hv = torch.empty((K, b), dtype=tdt, device=dev)
+        ht = torch.empty(K, dtype=tdt, device=dev)
+        nb = T.trbt_band_to_tridi_workspace_bytes(n, b, cplx)
+        buf = torch.empty(nb + T.TRBT_WORK_ALIGN, dtype=torch.uint8, device=dev)
+        off = (-buf.data_ptr()) % T.TRBT_WORK_ALIGN
+        work = buf[off: off + nb]
+        f = T.trbt_band_to_tridi_z if cplx else T.trbt_band_to_tridi_d
+
+        def run():
+            rc = f(n, b, abd, b + 1, d, e, hv, ht, work, nb, stream)
+            if rc:
+                raise T.TrbtError(rc, f.__name__)
+
+        for _ in range(warmup):
+            run()
+        torch.cuda.synchronize()
+        evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+               for _ in range(steps)]
+        for e0, e1 in evs:
+            e0.record(stream)
+            run()
+            e1.record(stream)
+        torch.cuda.synchronize()
+        if not bool(torch.isfinite(d).all()):
+            raise RuntimeError("bulge chase: a pipeline wait timed out")
+        ts = [a.elapsed_time(z) for a, z in evs]
+        ms = float(np.mean(ts))
+        fl = chase_flops(n, b, cplx)
+        period = n - 2 + n - 2 + (n - 2 + b - 1) // b     # 2 steps per stage + the first stage
+        r = {"n": n, "nbw": b, "dtype": "c128" if cplx else "f64", "reflectors": K,
+             "ms": round(ms, 3), "ms_min": round(min(ts), 3),
+             "pipeline_step_us": round(ms * 1e3 / period, 3),
+             "achieved_tflops": round(fl / (ms / 1e3) / 1e12, 4),
+             "peak_fp64_tflops": PEAK_FP64_TFLOPS}
+        if cpu:
+            import oracle
+            ns = 2048
+            abs_ = synth.band_matrix(ns, b, seed, dt, diag_shift=shift)
+            t = time.perf_counter()
+            oracle.band_to_tridiagonal(abs_, b)
+            cs = time.perf_counter() - t
+            est = cs * fl / chase_flops(ns, b, cplx)
+            r["cpu_oracle"] = {"sample": f"n={ns}, nbw={b}, same dtype; scaled by the flop count",
+                               "sample_s": round(cs, 3), "extrapolated_s": round(est, 1),
+                               "cores": 1, "kind": "oracle"}
+            r["speedup_vs_oracle"] = round(est / (ms / 1e3), 1)
+        log(f"chase {label}: {ms:.1f} ms")
+        res[label] = r
+    return res
+
+
 def committed_traffic(workload: str):
     """HBM bytes per launch of the apply kernel from the committed rocprofv3
     counter summary, if it was taken on the current kernel source; else None."""
@@ -346,6 +433,10 @@ def main():
                     help="skip the adjoint-vs-plain comparison on the differentiation workload")
     ap.add_argument("--adjoint-only", action="store_true",
                     help="run only the adjoint-vs-plain comparison and print its JSON")
+    ap.add_argument("--no-chase", action="store_true",
+                    help="skip the banded-to-tridiagonal bulge chasing leg")
+    ap.add_argument("--chase-only", action="store_true",
+                    help="run only the bulge chasing leg and print its JSON")
     ap.add_argument("--no-plain", action="store_true",
                     help="in the adjoint comparison, time only the hand-written adjoint")
     ap.add_argument("--copy-kernel", type=int, default=0, metavar="BYTES",
@@ -374,6 +465,10 @@ def main():
         print(json.dumps({"batched_vs_loop": batched_leg(args.steps, args.warmup),
                           "batched_complex_vs_loop": batched_leg(args.steps, args.warmup, "z")}),
               flush=True)
+        return
+    if args.chase_only:
+        print(json.dumps({"chase": chase_leg(args.steps, args.warmup,
+                                             not args.no_cpu_baseline)}), flush=True)
         return
     if args.adjoint_only:
         print(json.dumps({"adjoint_vs_plain": adjoint_leg(args.warmup, not args.no_plain)}),
@@ -470,6 +565,8 @@ def main():
         out["batched_complex_vs_loop"] = batched_leg(args.steps, args.warmup, "z")
     if not args.no_adjoint:
         out["adjoint_vs_plain"] = adjoint_leg(args.warmup, not args.no_plain)
+    if not args.no_chase:
+        out["chase"] = chase_leg(min(args.steps, 3), args.warmup, not args.no_cpu_baseline)
     if not args.no_cpu_baseline:
         log("timing the CPU oracle on a column sample")
         out["cpu_baseline"] = cpu_baseline(cfg, V, tau, Z, L_total)
