@@ -59,6 +59,8 @@ def lib():
         L.orc_apply_q_z.argtypes = [_i64, _i64, _i64, _i64, C.c_void_p, C.c_void_p,
                                     C.c_void_p, _i64]
         L.orc_adjoint_d.argtypes = [_i64, _i64, _i64, _dp, _dp, _dp, _i64, _dp, _i64, _dp, _dp]
+        L.orc_adjoint_z.argtypes = [_i64, _i64, _i64, C.c_void_p, C.c_void_p, C.c_void_p, _i64,
+                                    C.c_void_p, _i64, C.c_void_p, C.c_void_p]
         L.orc_tridi_ql.argtypes = [_i64, _dp, _dp, _dp, _i64]
         L.orc_jacobi_d.argtypes = [_i64, _dp, _dp, _dp]
         L.orc_num_threads.restype = C.c_int
@@ -194,9 +196,13 @@ def apply_q(Z: np.ndarray, hh_v, hh_tau, nbw: int) -> np.ndarray:
 
 
 def adjoint(Z_in: np.ndarray, G: np.ndarray, hh_v: np.ndarray, hh_tau: np.ndarray, nbw: int):
-    """Reverse-mode derivative of the real back-transformation
-    Z_out = H_0 ... H_{K-1} Z_in (Eq. 2stage_bkwd1, real reflectors).
-    G = dL/dZ_out (n, nev).  Returns (dL/dZ_in, dL/dv (K, nbw), dL/dtau (K,))."""
+    """Reverse-mode derivative of the back-transformation
+    Z_out = H_0 ... H_{K-1} Z_in (Eq. 2stage_bkwd1).
+    G = dL/dZ_out (n, nev).  Returns (dL/dZ_in, dL/dv (K, nbw), dL/dtau (K,)).
+    Complex inputs: conjugate-Wirtinger gradients (PyTorch's convention,
+    dL = Re sum conj(grad) dx)."""
+    if any(np.iscomplexobj(a) for a in (Z_in, G, hh_v, hh_tau)):
+        return _adjoint_z(Z_in, G, hh_v, hh_tau, nbw)
     Zi = np.array(Z_in, dtype=np.float64, order="F", copy=True)
     Gi = np.array(G, dtype=np.float64, order="F", copy=True)
     n, nev = Zi.shape
@@ -211,6 +217,24 @@ def adjoint(Z_in: np.ndarray, G: np.ndarray, hh_v: np.ndarray, hh_tau: np.ndarra
     ld = max(n, 1)
     _check(lib().orc_adjoint_d(n, nbw, nev, _p(hv), _p(ht), _p(Zi), ld, _p(Gi), ld, _p(dv),
                                _p(dt)), "adjoint")
+    return Gi, dv[:K], dt[:K]
+
+
+def _adjoint_z(Z_in, G, hh_v, hh_tau, nbw: int):
+    Zi = np.array(Z_in, dtype=np.complex128, order="F", copy=True)
+    Gi = np.array(G, dtype=np.complex128, order="F", copy=True)
+    n, nev = Zi.shape
+    K = num_reflectors(n, nbw)
+    hv = np.ascontiguousarray(hh_v, dtype=np.complex128)
+    ht = np.ascontiguousarray(hh_tau, dtype=np.complex128)
+    if hv.size == 0:
+        hv = np.zeros((1, nbw), np.complex128)
+        ht = np.zeros(1, np.complex128)
+    dv = np.zeros((max(K, 1), nbw), np.complex128)
+    dt = np.zeros(max(K, 1), np.complex128)
+    ld = max(n, 1)
+    _check(lib().orc_adjoint_z(n, nbw, nev, _v(hv), _v(ht), _v(Zi), ld, _v(Gi), ld, _v(dv),
+                               _v(dt)), "adjoint_z")
     return Gi, dv[:K], dt[:K]
 
 

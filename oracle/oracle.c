@@ -551,6 +551,103 @@ int orc_adjoint_d(int64_t n, int64_t b, int64_t nev, const double *hh_v,
 }
 
 /* ------------------------------------------------------------------------
+ * Adjoint of the complex back-transformation
+ *     Z_out = H_0 H_1 ... H_{K-1} Z_in,   H_k = I - tau_k v_k v_k^H
+ * (Eq. 2stage_bkwd1 with complex reflectors), for a real loss L, in the
+ * convention of the conjugate Wirtinger derivative that PyTorch uses: the
+ * gradient of x is grad_x with  dL = Re sum conj(grad_x) dx  for every
+ * complex perturbation dx (the steepest-ascent direction).
+ * Chain rule for y = f(x, conj x):  grad_x = J^H grad_y + J'^T conj(grad_y)
+ * with J = dy/dx, J' = dy/d(conj x).  For one column update
+ *     z' = z - tau v (v^H z),   w = v^H z,  gamma = v^H g  (g = grad_z'):
+ *   grad_z   = g - conj(tau) v gamma              (= H^H g)
+ *   grad_tau = -conj(w) gamma
+ *   grad_v   = -conj(tau) conj(w) g - tau conj(gamma) z
+ *     (the first term from v itself, the second from v^H, through which
+ *     conj(v) enters).
+ * The real adjoint is the special case with every imaginary part zero.
+ * Same sweep structure as orc_adjoint_d: per column a forward pass that
+ * records the rows entering each reflector (the tape), then the reflectors
+ * in generation order; dv, dtau summed over columns, per thread, threads in
+ * order.
+ * ---------------------------------------------------------------------- */
+int orc_adjoint_z(int64_t n, int64_t b, int64_t nev, const zc *hh_v, const zc *hh_tau,
+                  const zc *Zin, int64_t ldz, zc *G, int64_t ldg, zc *dv, zc *dtau)
+{
+    if (n < 0 || b < 1 || nev < 0 || ldz < (n > 1 ? n : 1) || ldg < (n > 1 ? n : 1))
+        return ORC_EARG;
+    const int64_t K = orc_num_reflectors(n, b);
+    for (int64_t i = 0; i < K * b; ++i) dv[i] = 0.0;
+    for (int64_t k = 0; k < K; ++k) dtau[k] = 0.0;
+    if (K == 0 || nev == 0) return ORC_OK;
+    int64_t *r0 = malloc(sizeof(int64_t) * K);
+    int64_t *ln = malloc(sizeof(int64_t) * K);
+    int64_t *toff = malloc(sizeof(int64_t) * (K + 1));
+    if (!r0 || !ln || !toff) { free(r0); free(ln); free(toff); return ORC_ENOMEM; }
+    orc_reflector_table(n, b, NULL, NULL, r0, ln);
+    toff[0] = 0;
+    for (int64_t k = 0; k < K; ++k) toff[k + 1] = toff[k] + ln[k];
+    const int nt = omp_get_max_threads();
+    zc *acc_v = calloc((size_t)nt * K * b, sizeof(zc));
+    zc *acc_t = calloc((size_t)nt * K, sizeof(zc));
+    int fail = !acc_v || !acc_t;
+    if (!fail) {
+#pragma omp parallel num_threads(nt)
+        {
+            const int me = omp_get_thread_num();
+            zc *av = acc_v + (size_t)me * K * b, *at = acc_t + (size_t)me * K;
+            zc *tape = malloc(sizeof(zc) * toff[K]);
+            zc *z = malloc(sizeof(zc) * (n > 0 ? n : 1));
+            if (!tape || !z) {
+#pragma omp atomic write
+                fail = 1;
+            } else {
+#pragma omp for schedule(static)
+                for (int64_t c = 0; c < nev; ++c) {
+                    for (int64_t i = 0; i < n; ++i) z[i] = Zin[c * ldz + i];
+                    for (int64_t k = K - 1; k >= 0; --k) {
+                        const zc *v = hh_v + k * b;
+                        zc *zz = z + r0[k];
+                        zc d = 0.0;
+                        for (int64_t i = 0; i < ln[k]; ++i) {
+                            tape[toff[k] + i] = zz[i];
+                            d += conj(v[i]) * zz[i];
+                        }
+                        const zc a = hh_tau[k] * d;
+                        for (int64_t i = 0; i < ln[k]; ++i) zz[i] -= a * v[i];
+                    }
+                    zc *g = G + c * ldg;
+                    for (int64_t k = 0; k < K; ++k) {
+                        const zc *v = hh_v + k * b, *zk = tape + toff[k];
+                        zc *gg = g + r0[k];
+                        zc gam = 0.0, w = 0.0;
+                        for (int64_t i = 0; i < ln[k]; ++i) {
+                            gam += conj(v[i]) * gg[i];
+                            w += conj(v[i]) * zk[i];
+                        }
+                        const zc t = hh_tau[k];
+                        at[k] -= conj(w) * gam;
+                        for (int64_t i = 0; i < ln[k]; ++i)
+                            av[k * b + i] -= conj(t) * conj(w) * gg[i] + t * conj(gam) * zk[i];
+                        for (int64_t i = 0; i < ln[k]; ++i) gg[i] -= conj(t) * gam * v[i];
+                    }
+                }
+            }
+            free(tape);
+            free(z);
+        }
+    }
+    if (!fail) {
+        for (int th = 0; th < nt; ++th) {
+            for (int64_t i = 0; i < K * b; ++i) dv[i] += acc_v[(size_t)th * K * b + i];
+            for (int64_t k = 0; k < K; ++k) dtau[k] += acc_t[(size_t)th * K + k];
+        }
+    }
+    free(acc_v); free(acc_t); free(r0); free(ln); free(toff);
+    return fail ? ORC_ENOMEM : ORC_OK;
+}
+
+/* ------------------------------------------------------------------------
  * Symmetric tridiagonal eigensolver, Eq. 2stage_solve, by the implicit QL
  * algorithm with Wilkinson shift (Golub & Van Loan, Sec. 8.3; the paper
  * itself uses divide and conquer, which reaches the same eigenpairs).
