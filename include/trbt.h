@@ -190,6 +190,30 @@ int trans_ev_tridi_to_band_bwd_ckpt_d(int64_t n, int nbw, int64_t nev,
                                       int ckpt_every, void *work, size_t work_bytes,
                                       void *stream);
 
+/* Adjoint of the complex back-transformation (H_k = I - tau_k v_k v_k^H,
+ * complex tau) for a real scalar L, in the conjugate-Wirtinger convention:
+ * every returned gradient grad_x satisfies dL = Re sum conj(grad_x) dx for
+ * complex perturbations dx (the convention of PyTorch's complex autograd).
+ * On entry G = grad of Z_out; on exit
+ *   grad Z_in = H_{K-1}^H ... H_0^H G        (in place in G),
+ *   grad v_k  = sum over columns of -conj(tau_k) conj(w) g - tau_k conj(gamma) z,
+ *   grad tau_k = sum over columns of -conj(w) gamma,
+ * with z the column rows entering H_k in the forward pass, g the gradient
+ * rows leaving it, w = v_k^H z and gamma = v_k^H g.  Computed by the
+ * streaming form (one lane per column, checkpoints every 16 stages,
+ * fixed-order column sums: bitwise reproducible) for every nbw.
+ * Arguments, validation and status codes as trans_ev_tridi_to_band_adjoint_d,
+ * with complex hh_v, hh_tau, Z_in, G, dv, dtau and the workspace size from
+ * trbt_adjoint_workspace_bytes_z. */
+int trbt_adjoint_workspace_bytes_z(int64_t n, int nbw, int64_t nev, int ckpt_every,
+                                   size_t *bytes);
+int trans_ev_tridi_to_band_adjoint_z(int64_t n, int nbw, int64_t nev,
+                                     const trbt_z *hh_v, const trbt_z *hh_tau,
+                                     const trbt_z *Z_in, int64_t ldz,
+                                     trbt_z *G, int64_t ldg,
+                                     trbt_z *dv, trbt_z *dtau, int ckpt_every,
+                                     void *work, size_t work_bytes, void *stream);
+
 /* ------------------------------------------------------------------------
  * Batched back-transformation: many independent problems of uneven size
  * (k-points, spin channels), all real or all complex, each exactly the

@@ -26,6 +26,7 @@ __all__ = [
     "trans_ev_tridi_to_band_adjoint_d", "trans_ev_tridi_to_band_fwd_ckpt_d",
     "trans_ev_tridi_to_band_bwd_ckpt_d", "adjoint", "BackTransform", "back_transform_autograd",
     "trbt_band_to_tridi_workspace_bytes", "trbt_band_to_tridi_d", "trbt_band_to_tridi_z",
+    "trbt_adjoint_workspace_bytes_z", "trans_ev_tridi_to_band_adjoint_z",
     "band_to_tridiagonal",
 ]
 
@@ -89,6 +90,11 @@ def lib():
         L.trans_ev_tridi_to_band_bwd_ckpt_d.argtypes = [i64, i32, i64, vp, vp, vp, i64, vp, vp,
                                                         i32, vp, sz, vp]
         L.trans_ev_tridi_to_band_bwd_ckpt_d.restype = i32
+        L.trbt_adjoint_workspace_bytes_z.argtypes = [i64, i32, i64, i32, C.POINTER(sz)]
+        L.trbt_adjoint_workspace_bytes_z.restype = i32
+        L.trans_ev_tridi_to_band_adjoint_z.argtypes = \
+            L.trans_ev_tridi_to_band_adjoint_d.argtypes
+        L.trans_ev_tridi_to_band_adjoint_z.restype = i32
         L.trbt_band_to_tridi_workspace_bytes.argtypes = [i64, i32, i32, C.POINTER(sz)]
         L.trbt_band_to_tridi_workspace_bytes.restype = i32
         for f in (L.trbt_band_to_tridi_d, L.trbt_band_to_tridi_z):
@@ -363,6 +369,22 @@ def trans_ev_tridi_to_band_adjoint_d(n, nbw, nev, hh_v, hh_tau, Z_in, ldz, G, ld
         _ptr(dtau), ckpt_every, _ptr(work), work_bytes, _stream(stream))
 
 
+def trbt_adjoint_workspace_bytes_z(n: int, nbw: int, nev: int, ckpt_every: int = 16) -> int:
+    b = C.c_size_t()
+    rc = lib().trbt_adjoint_workspace_bytes_z(n, nbw, nev, ckpt_every, C.byref(b))
+    if rc:
+        raise TrbtError(rc, "trbt_adjoint_workspace_bytes_z")
+    return b.value
+
+
+def trans_ev_tridi_to_band_adjoint_z(n, nbw, nev, hh_v, hh_tau, Z_in, ldz, G, ldg, dv, dtau,
+                                     ckpt_every, work, work_bytes, stream=None) -> int:
+    """Status-returning call of the C entry point (complex)."""
+    return lib().trans_ev_tridi_to_band_adjoint_z(
+        n, nbw, nev, _ptr(hh_v), _ptr(hh_tau), _ptr(Z_in), ldz, _ptr(G), ldg, _ptr(dv),
+        _ptr(dtau), ckpt_every, _ptr(work), work_bytes, _stream(stream))
+
+
 def trans_ev_tridi_to_band_fwd_ckpt_d(n, nbw, nev, hh_v, hh_tau, Z, ldz, ckpt_every, work,
                                       work_bytes, stream=None) -> int:
     return lib().trans_ev_tridi_to_band_fwd_ckpt_d(
@@ -377,9 +399,9 @@ def trans_ev_tridi_to_band_bwd_ckpt_d(n, nbw, nev, hh_v, hh_tau, G, ldg, dv, dta
         _ptr(work), work_bytes, _stream(stream))
 
 
-def _adjoint_workspace(n, nbw, nev, device):
+def _adjoint_workspace(n, nbw, nev, device, cplx=False):
     import torch
-    nb = trbt_adjoint_workspace_bytes_d(n, nbw, nev)
+    nb = (trbt_adjoint_workspace_bytes_z if cplx else trbt_adjoint_workspace_bytes_d)(n, nbw, nev)
     if not nb:
         return None, 0
     buf = torch.empty(nb + TRBT_WORK_ALIGN, dtype=torch.uint8, device=device)
@@ -399,31 +421,33 @@ def _colmajor(t):
 def adjoint(Z_in, G, hh_v, hh_tau, nbw: int, work=None, stream=None):
     """dL/dZ_in, dL/dv, dL/dtau of Z_out = H_0..H_{K-1} Z_in for G = dL/dZ_out.
 
-    Z_in, G: (n, nev) float64 tensors with unit row stride (column-major
-    views); G is overwritten with dL/dZ_in.  Returns (G, dv (K, nbw), dtau (K,))."""
+    Z_in, G: (n, nev) float64 or complex128 tensors with unit row stride
+    (column-major views); G is overwritten with dL/dZ_in.  Complex: the
+    conjugate-Wirtinger gradients of a real L (PyTorch's convention).
+    Returns (G, dv (K, nbw), dtau (K,))."""
     import torch
     n, nev = Z_in.shape
+    cplx = Z_in.dtype == torch.complex128
+    want = torch.complex128 if cplx else torch.float64
+    for name, t in (("Z_in", Z_in), ("G", G), ("hh_v", hh_v), ("hh_tau", hh_tau)):
+        if t.dtype != want:
+            raise TypeError(f"{name} must be {want} like Z_in (float64 or complex128)")
     for name, t in (("Z_in", Z_in), ("G", G)):
-        if t.dtype != torch.float64:
-            raise TypeError(f"{name} must be float64")
         if nev and n and t.stride(0) != 1:
             raise ValueError(f"{name} must be column-major (unit row stride)")
     K = trbt_num_reflectors(n, nbw)
-    dv = torch.empty(max(K, 1), nbw, dtype=torch.float64, device=G.device)[:K]
-    dt = torch.empty(max(K, 1), dtype=torch.float64, device=G.device)[:K]
+    dv = torch.empty(max(K, 1), nbw, dtype=want, device=G.device)[:K]
+    dt = torch.empty(max(K, 1), dtype=want, device=G.device)[:K]
     if work is None:
-        nb = trbt_adjoint_workspace_bytes_d(n, nbw, nev)
-        if nb:
-            buf = torch.empty(nb + TRBT_WORK_ALIGN, dtype=torch.uint8, device=G.device)
-            work = buf[(-buf.data_ptr()) % TRBT_WORK_ALIGN:][:nb]
+        work, _ = _adjoint_workspace(n, nbw, nev, G.device, cplx)
     wb = 0 if work is None else work.numel() * work.element_size()
     ldz = Z_in.stride(1) if nev > 1 else max(n, 1)
     ldg = G.stride(1) if nev > 1 else max(n, 1)
-    rc = trans_ev_tridi_to_band_adjoint_d(n, nbw, nev, hh_v, hh_tau, Z_in, max(ldz, 1), G,
-                                          max(ldg, 1), dv if K else None, dt if K else None,
-                                          16, work, wb, stream)
+    f = trans_ev_tridi_to_band_adjoint_z if cplx else trans_ev_tridi_to_band_adjoint_d
+    rc = f(n, nbw, nev, hh_v, hh_tau, Z_in, max(ldz, 1), G, max(ldg, 1), dv if K else None,
+           dt if K else None, 16, work, wb, stream)
     if rc:
-        raise TrbtError(rc, "trans_ev_tridi_to_band_adjoint_d")
+        raise TrbtError(rc, f.__name__)
     return G, dv, dt
 
 
@@ -431,12 +455,15 @@ def _back_transform_function():
     import torch
 
     class BackTransform(torch.autograd.Function):
-        """Z_out = H_0 ... H_{K-1} Z_in (real) with the hand-written adjoint.
+        """Z_out = H_0 ... H_{K-1} Z_in with the hand-written adjoint.
 
-        The forward pass runs the checkpointing forward kernel and keeps its
-        workspace (a checkpoint every 16 stages, not the states in between)
-        for the backward pass, which recomputes the states inside each
-        16-stage block from it."""
+        Real: the forward pass runs the checkpointing forward kernel and
+        keeps its workspace (a checkpoint every 16 stages, not the states in
+        between) for the backward pass, which recomputes the states inside
+        each 16-stage block from it.  Complex: the forward pass is the plain
+        transformation; the backward pass runs the one-call complex adjoint
+        from the saved Z_in (conjugate-Wirtinger gradients, as PyTorch's
+        complex autograd expects)."""
 
         @staticmethod
         def forward(ctx, Z_in, hh_v, hh_tau, nbw):
@@ -444,8 +471,15 @@ def _back_transform_function():
             n, nev = out.shape
             v = hh_v.detach().contiguous()
             t = hh_tau.detach().contiguous()
-            if v.dtype != torch.float64 or out.dtype != torch.float64:
-                raise TypeError("the differentiable back-transformation is real FP64")
+            if out.dtype == torch.complex128 and v.dtype == out.dtype and t.dtype == out.dtype:
+                back_transform(out, v, t, nbw)
+                ctx.save_for_backward(v, t, Z_in.detach().clone())
+                ctx.cplx, ctx.nbw, ctx.shape = True, nbw, (n, nev)
+                return out
+            if v.dtype != torch.float64 or out.dtype != torch.float64 or t.dtype != torch.float64:
+                raise TypeError("the differentiable back-transformation takes float64 or "
+                                "complex128 (Z_in, hh_v, hh_tau of one dtype)")
+            ctx.cplx = False
             work, nb = _adjoint_workspace(n, nbw, nev, out.device)
             rc = trans_ev_tridi_to_band_fwd_ckpt_d(n, nbw, nev, v, t, out, max(n, 1), 16, work,
                                                    nb)
@@ -457,6 +491,12 @@ def _back_transform_function():
 
         @staticmethod
         def backward(ctx, grad_out):
+            if ctx.cplx:
+                v, t, zin = ctx.saved_tensors
+                _, zc = _colmajor(zin)
+                gbuf, g = _colmajor(grad_out.to(torch.complex128))
+                g, dv, dt = adjoint(zc, g, v, t, ctx.nbw)
+                return g, dv, dt, None
             v, t = ctx.saved_tensors
             n, nev = ctx.shape
             gbuf, g = _colmajor(grad_out)
@@ -479,7 +519,8 @@ class _Lazy:
 
 
 def back_transform_autograd(Z_in, hh_v, hh_tau, nbw: int):
-    """Differentiable real back-transformation (torch.autograd)."""
+    """Differentiable back-transformation (torch.autograd), float64 or complex128
+    (complex: conjugate-Wirtinger gradients, PyTorch's convention)."""
     if _Lazy.fn is None:
         _Lazy.fn = _back_transform_function()
     return _Lazy.fn.apply(Z_in, hh_v, hh_tau, nbw)

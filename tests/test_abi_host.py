@@ -178,10 +178,12 @@ def test_complex_plan_validation_codes(T):
     assert h.value is None
 
 
-def test_adjoint_validation_codes(T):
-    """The adjoint entry point checks its 15 arguments on the host, in order,
-    before any HIP call."""
-    f = T.trans_ev_tridi_to_band_adjoint_d
+@pytest.mark.parametrize("sfx", ["d", "z"])
+def test_adjoint_validation_codes(T, sfx):
+    """The adjoint entry points check their 15 arguments on the host, in
+    order, before any HIP call."""
+    f = getattr(T, "trans_ev_tridi_to_band_adjoint_" + sfx)
+    wsb = getattr(T, "trbt_adjoint_workspace_bytes_" + sfx)
     ok = dict(n=100, nbw=32, nev=10, hh_v=FAKE, hh_tau=FAKE, Z_in=FAKE, ldz=100, G=FAKE, ldg=100,
               dv=FAKE, dtau=FAKE, ckpt=16, work=None, wb=0)
 
@@ -205,13 +207,13 @@ def test_adjoint_validation_codes(T):
     assert call(work=FAKE + 8) == -13
     assert call(work=None, wb=64) == -13
     assert call(nbw=1, hh_v=None, hh_tau=None, dv=None, dtau=None) == 0   # K == 0: no-op
-    assert T.trbt_adjoint_workspace_bytes_d(100, 32, 10, 16) > 0
-    assert T.trbt_adjoint_workspace_bytes_d(100, 32, 0, 16) == 0
-    assert T.trbt_adjoint_workspace_bytes_d(100, 1, 10, 16) == 0
+    assert wsb(100, 32, 10, 16) > 0
+    assert wsb(100, 32, 0, 16) == 0
+    assert wsb(100, 1, 10, 16) == 0
     for bad, code in [((-1, 32, 10, 16), -1), ((100, 0, 10, 16), -2), ((100, 32, 200, 16), -3),
                       ((100, 32, 10, 5), -4)]:
         with pytest.raises(T.TrbtError) as e:
-            T.trbt_adjoint_workspace_bytes_d(*bad)
+            wsb(*bad)
         assert e.value.status == code
 
 

@@ -1,0 +1,135 @@
+"""GPU parity of the adjoint of the complex back-transformation (conjugate-
+Wirtinger gradients of a real loss, PyTorch's convention), through the C ABI,
+against the CPU oracle's complex adjoint and torch.autograd.gradcheck.
+
+Tolerance: relative Frobenius error <= 1e-12 for grad Z_in, grad v and
+grad tau, each compared as a whole array.  The GPU runs the same per-column
+recurrences as the oracle (one lane per column, the same summation order
+inside a column); only the column sums behind grad v and grad tau are taken
+in a different order (64 columns of a wave, then waves in order, against
+the oracle's per-thread blocks), which moves them by ~1e-15 relative.
+"""
+import numpy as np
+import pytest
+
+from conftest import gpu_available
+
+pytestmark = [pytest.mark.gpu,
+              pytest.mark.skipif(not gpu_available(), reason="needs a GPU")]
+
+TOL = 1e-12
+
+
+def _relerr(a, b):
+    return np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-300)
+
+
+def _inputs(n, nbw, nev, seed, general_tau=False):
+    import synth
+    lengths = synth.reflector_lengths(n, nbw)
+    V, tau = synth.unitary_reflectors(lengths, nbw, seed, "z")
+    if general_tau:
+        rng = np.random.default_rng(seed + 7)
+        tau = rng.uniform(0.3, 1.7, len(tau)) + 1j * rng.uniform(-0.8, 0.8, len(tau))
+    Z = synth.gaussian(n, nev, seed + 1, "z")
+    G = synth.gaussian(n, nev, seed + 2, "z")
+    return Z, G, V, tau
+
+
+def gpu_adjoint_z(Z, G, V, tau, nbw):
+    import torch
+    import paper_2002_10991_amd as T
+    n, nev = Z.shape
+    print(f"[gpu] adjoint_z n={n} nbw={nbw} nev={nev}", flush=True)
+    zb = torch.from_numpy(np.ascontiguousarray(Z.T)).to("cuda")
+    gb = torch.from_numpy(np.ascontiguousarray(G.T)).to("cuda")
+    g, dv, dt = T.adjoint(zb.T, gb.T, torch.from_numpy(V).to("cuda"),
+                          torch.from_numpy(tau).to("cuda"), nbw)
+    torch.cuda.synchronize()
+    return g.cpu().numpy(), dv.cpu().numpy(), dt.cpu().numpy()
+
+
+SHAPES = [(40, 16, 17), (100, 16, 33), (150, 32, 65), (300, 64, 64), (301, 64, 63),
+          (61, 3, 20), (90, 8, 31), (129, 31, 64), (100, 128, 10), (70, 2, 5)]
+
+
+@pytest.mark.parametrize("n,nbw,nev", SHAPES)
+def test_complex_adjoint_vs_oracle(oracle_mod, n, nbw, nev):
+    Z, G, V, tau = _inputs(n, nbw, nev, 500 + n + nbw)
+    rZ, rv, rt = oracle_mod.adjoint(Z, G, V, tau, nbw)
+    gZ, gv, gt = gpu_adjoint_z(Z, G, V, tau, nbw)
+    assert _relerr(gZ, rZ) <= TOL
+    assert _relerr(gv, rv) <= TOL
+    assert _relerr(gt, rt) <= TOL
+
+
+@pytest.mark.parametrize("n,nbw,nev", [(120, 16, 40), (97, 7, 10)])
+def test_complex_adjoint_general_tau(oracle_mod, n, nbw, nev):
+    Z, G, V, tau = _inputs(n, nbw, nev, 900 + n, general_tau=True)
+    rZ, rv, rt = oracle_mod.adjoint(Z, G, V, tau, nbw)
+    gZ, gv, gt = gpu_adjoint_z(Z, G, V, tau, nbw)
+    assert _relerr(gZ, rZ) <= TOL and _relerr(gv, rv) <= TOL and _relerr(gt, rt) <= TOL
+
+
+def test_complex_adjoint_deterministic():
+    Z, G, V, tau = _inputs(200, 32, 70, 31)
+    a = gpu_adjoint_z(Z, G, V, tau, 32)
+    b = gpu_adjoint_z(Z, G, V, tau, 32)
+    for x, y in zip(a, b):
+        assert np.array_equal(x, y)
+
+
+def test_complex_adjoint_degenerate(oracle_mod):
+    import torch
+    import paper_2002_10991_amd as T
+    # nev = 0: zero parameter gradients
+    Z, G, V, tau = _inputs(50, 8, 3, 41)
+    vd, td = torch.from_numpy(V).to("cuda"), torch.from_numpy(tau).to("cuda")
+    z0 = torch.zeros((0, 50), dtype=torch.complex128, device="cuda")
+    _, dv, dt = T.adjoint(z0.T, z0.clone().T, vd, td, 8)
+    torch.cuda.synchronize()
+    assert dv.shape == V.shape and not dv.abs().any() and not dt.abs().any()
+    # nbw = 1: no reflectors, grad Z_in = G
+    gb = torch.from_numpy(np.ascontiguousarray(G.T)).to("cuda")
+    zb = torch.from_numpy(np.ascontiguousarray(Z.T)).to("cuda")
+    e = torch.zeros((0, 1), dtype=torch.complex128, device="cuda")
+    g, dv, dt = T.adjoint(zb.T, gb.T, e, e[:, 0], 1)
+    torch.cuda.synchronize()
+    assert np.array_equal(g.cpu().numpy(), G) and dv.numel() == 0
+
+
+def test_complex_autograd_gradcheck():
+    import torch
+    import paper_2002_10991_amd as T
+    n, nbw, nev = 10, 3, 2
+    Z, _, V, tau = _inputs(n, nbw, nev, 77, general_tau=True)
+    print(f"[gpu] gradcheck complex n={n} nbw={nbw} nev={nev}", flush=True)
+    args = [torch.from_numpy(np.ascontiguousarray(a)).to("cuda").requires_grad_(True)
+            for a in (Z, V, tau)]
+    assert torch.autograd.gradcheck(lambda z, v, t: T.back_transform_autograd(z, v, t, nbw),
+                                    args, eps=1e-6, atol=1e-7, rtol=1e-6)
+
+
+def test_complex_autograd_matches_oracle(oracle_mod):
+    import torch
+    import paper_2002_10991_amd as T
+    n, nbw, nev = 150, 32, 20
+    Z, G, V, tau = _inputs(n, nbw, nev, 88)
+    Zt, Vt, tt = (torch.from_numpy(np.ascontiguousarray(a)).to("cuda").requires_grad_(True)
+                  for a in (Z, V, tau))
+    Gt = torch.from_numpy(G).to("cuda")
+    # L = Re sum conj(G) Y: its gradient with respect to Y is G
+    torch.real(torch.sum(torch.conj(Gt) * T.back_transform_autograd(Zt, Vt, tt, nbw))).backward()
+    rZ, rv, rt = oracle_mod.adjoint(Z, G, V, tau, nbw)
+    for got, ref in ((Zt.grad, rZ), (Vt.grad, rv), (tt.grad, rt)):
+        assert _relerr(got.cpu().numpy(), ref) <= TOL
+
+
+def test_complex_adjoint_full_n_column_subset(oracle_mod):
+    # n and nbw of the differentiation workload, 64 columns (the oracle's
+    # cost grows with the columns; the GPU runs them as one wave)
+    n, nbw, nev = 4096, 64, 64
+    Z, G, V, tau = _inputs(n, nbw, nev, 2005)
+    rZ, rv, rt = oracle_mod.adjoint(Z, G, V, tau, nbw)
+    gZ, gv, gt = gpu_adjoint_z(Z, G, V, tau, nbw)
+    assert _relerr(gZ, rZ) <= TOL and _relerr(gv, rv) <= TOL and _relerr(gt, rt) <= TOL
