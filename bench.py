@@ -168,7 +168,8 @@ def plain_adjoint(Z, G, V, tau, nbw):
     through a per-stage implementation (one batched gather / bmm / update /
     index_copy per stage, all slots of the stage at once), with
     torch.utils.checkpoint over 16-stage segments so that memory stays
-    bounded.  Returns (dL/dZ_in, dL/dv, dL/dtau) for L = <G, Z_out>."""
+    bounded.  Returns (dL/dZ_in, dL/dv, dL/dtau) for L = <G, Z_out> (complex:
+    L = Re sum conj(G) Z_out, conjugate-Wirtinger gradients)."""
     import torch
     from torch.utils.checkpoint import checkpoint
     dev = Z.device
@@ -192,7 +193,8 @@ def plain_adjoint(Z, G, V, tau, nbw):
         a, b = int(off[s]), int(off[s + 1])
         v = Vg[a:b]                                       # (S, nbw), zero beyond len
         W = Zp[rows.reshape(-1)].reshape(rows.shape[0], nbw, nev)
-        d = torch.bmm(v.unsqueeze(1), W)                  # (S, 1, nev)
+        vh = v.conj() if v.is_complex() else v
+        d = torch.bmm(vh.unsqueeze(1), W)                 # (S, 1, nev): v^H W
         W2 = W - tg[a:b, None, None] * v.unsqueeze(2) * d
         return Zp.index_copy(0, rows.reshape(-1), W2.reshape(-1, nev))
 
@@ -207,7 +209,7 @@ def plain_adjoint(Z, G, V, tau, nbw):
         lo = max(s - 15, 0)
         Zp = checkpoint(segment, Zp, s, lo, use_reentrant=False)
         s = lo - 1
-    loss = (Zp[:n] * G).sum()
+    loss = torch.real((Zp[:n] * G.conj()).sum()) if Z.is_complex() else (Zp[:n] * G).sum()
     loss.backward()
     return Zin.grad, Vg.grad, tg.grad
 
@@ -308,6 +310,77 @@ def adjoint_leg(warmup: int, plain: bool = True):
         "max_rel_diff_vs_plain": {"dZ_in": rel(Gbuf.t(), pz), "dv": rel(dv, pv),
                                   "dtau": rel(dt, pt)},
     })
+    return out
+
+
+def adjoint_complex_leg(warmup: int, plain: bool = True):
+    """The complex variant of the differentiation workload (n=4096, nbw=64,
+    nev=2048, complex Hermitian reflectors and Z, G seed 2005): forward plus
+    the one-call complex adjoint (streaming form) against the plain form."""
+    import torch
+    import paper_2002_10991_amd as T
+    import synth
+    dev = torch.device("cuda:0")
+    n, nbw, nev = 4096, 64, 2048
+    lengths = synth.reflector_lengths(n, nbw)
+    V, tau = synth.unitary_reflectors(lengths, nbw, 1005, "z")
+    Zh = synth.gaussian(n, nev, 1006, "z")
+    Gh = synth.gaussian(n, nev, 2005, "z")
+    L = int(lengths.sum())
+    Vd, td = torch.from_numpy(V).to(dev), torch.from_numpy(tau).to(dev)
+    Zbuf = torch.from_numpy(np.ascontiguousarray(Zh.T)).to(dev)
+    Gsrc = torch.from_numpy(np.ascontiguousarray(Gh.T)).to(dev)
+    Obuf, Gbuf = torch.empty_like(Zbuf), torch.empty_like(Gsrc)
+    K = len(tau)
+    dv = torch.empty(K, nbw, dtype=torch.complex128, device=dev)
+    dt = torch.empty(K, dtype=torch.complex128, device=dev)
+    fw = T.alloc_workspace(n, nbw, nev, True, dev)
+    nb = T.trbt_adjoint_workspace_bytes_z(n, nbw, nev)
+    abuf = torch.empty(nb + T.TRBT_WORK_ALIGN, dtype=torch.uint8, device=dev)
+    aw = abuf[(-abuf.data_ptr()) % T.TRBT_WORK_ALIGN:][:nb]
+    stream = torch.cuda.current_stream()
+
+    def ours():
+        Obuf.copy_(Zbuf)
+        Gbuf.copy_(Gsrc)
+        rc = T.trans_ev_tridi_to_band_z(n, nbw, nev, Vd, td, Obuf, n, fw, fw.numel(), stream)
+        rc = rc or T.trans_ev_tridi_to_band_adjoint_z(n, nbw, nev, Vd, td, Zbuf, n, Gbuf, n, dv,
+                                                      dt, 16, aw, nb, stream)
+        if rc:
+            raise T.TrbtError(rc, "complex adjoint leg")
+
+    for _ in range(max(warmup, 1)):
+        ours()
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    ours()
+    e1.record(stream)
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1)
+    log(f"C5 complex forward + one-call adjoint: {ms:.1f} ms")
+    flops = 4 * 18 * L * nev
+    out = {
+        "workload": "C5 complex: n=4096, nbw=64, nev=2048, forward + adjoint (streaming form), "
+                    "G seed 2005",
+        "flops_counted": flops, "ours_ms": round(ms, 2),
+        "ours_tflops": round(flops / ms / 1e9, 4),
+        "ours_form": "trans_ev_tridi_to_band_z + trans_ev_tridi_to_band_adjoint_z",
+    }
+    if not plain:
+        return out
+    t = time.perf_counter()
+    pz, pv, pt = plain_adjoint(Zbuf.t(), Gsrc.t(), Vd, td, nbw)
+    torch.cuda.synchronize()
+    plain_ms = (time.perf_counter() - t) * 1e3
+    log(f"C5 complex plain form: {plain_ms:.1f} ms")
+
+    def rel(a, b):
+        return float(torch.linalg.norm(a - b) / torch.linalg.norm(b))
+
+    out.update({"plain_ms": round(plain_ms, 1), "speedup_vs_plain": round(plain_ms / ms, 3),
+                "max_rel_diff_vs_plain": {"dZ_in": rel(Gbuf.t(), pz), "dv": rel(dv, pv),
+                                          "dtau": rel(dt, pt)}})
     return out
 
 
@@ -471,7 +544,9 @@ def main():
                                              not args.no_cpu_baseline)}), flush=True)
         return
     if args.adjoint_only:
-        print(json.dumps({"adjoint_vs_plain": adjoint_leg(args.warmup, not args.no_plain)}),
+        print(json.dumps({"adjoint_vs_plain": adjoint_leg(args.warmup, not args.no_plain),
+                          "adjoint_complex_vs_plain":
+                              adjoint_complex_leg(args.warmup, not args.no_plain)}),
               flush=True)
         return
 
@@ -565,6 +640,7 @@ def main():
         out["batched_complex_vs_loop"] = batched_leg(args.steps, args.warmup, "z")
     if not args.no_adjoint:
         out["adjoint_vs_plain"] = adjoint_leg(args.warmup, not args.no_plain)
+        out["adjoint_complex_vs_plain"] = adjoint_complex_leg(args.warmup, not args.no_plain)
     if not args.no_chase:
         out["chase"] = chase_leg(min(args.steps, 3), args.warmup, not args.no_cpu_baseline)
     if not args.no_cpu_baseline:

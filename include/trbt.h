@@ -199,9 +199,15 @@ int trans_ev_tridi_to_band_bwd_ckpt_d(int64_t n, int nbw, int64_t nev,
  *   grad v_k  = sum over columns of -conj(tau_k) conj(w) g - tau_k conj(gamma) z,
  *   grad tau_k = sum over columns of -conj(w) gamma,
  * with z the column rows entering H_k in the forward pass, g the gradient
- * rows leaving it, w = v_k^H z and gamma = v_k^H g.  Computed by the
- * streaming form (one lane per column, checkpoints every 16 stages,
- * fixed-order column sums: bitwise reproducible) for every nbw.
+ * rows leaving it, w = v_k^H z and gamma = v_k^H g.  Computed stage by
+ * stage (the slots of a stage are disjoint, Sec. 2.2.2: one launch per
+ * stage over all slots and columns) on row-major working copies of Z and G,
+ * with the rows a 16-stage segment touches checkpointed before it and the
+ * segment recomputed in the reverse sweep; the column sums behind dv and
+ * dtau are taken in a fixed order (bitwise reproducible).  Any nbw.
+ * Workspace: two working copies (2 n nev complex), the checkpoints (about
+ * n^2 nev / 32 complex), one segment's tape (about 16 n nev complex) and
+ * the per-256-column partial sums ((nev/256) K (nbw+1) complex).
  * Arguments, validation and status codes as trans_ev_tridi_to_band_adjoint_d,
  * with complex hh_v, hh_tau, Z_in, G, dv, dtau and the workspace size from
  * trbt_adjoint_workspace_bytes_z. */

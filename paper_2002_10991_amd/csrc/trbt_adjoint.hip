@@ -564,49 +564,26 @@ __device__ inline void apply_real(double* z, const double* __restrict__ v, doubl
     for (int i = 0; i < len; ++i) z[i] = fma(-a, v[i], z[i]);
 }
 
-// complex: z <- z - tau v (v^H z); all arrays interleaved (re, im)
-__device__ inline void apply_cplx(double* z, const double* __restrict__ v, const double* tau,
-                                  int len)
-{
-    double dr = 0.0, di = 0.0;
-    for (int i = 0; i < len; ++i) {
-        const double vr = v[2 * i], vi = v[2 * i + 1], zr = z[2 * i], zi = z[2 * i + 1];
-        dr = fma(vr, zr, fma(vi, zi, dr));
-        di = fma(vr, zi, fma(-vi, zr, di));
-    }
-    const double ar = tau[0] * dr - tau[1] * di, ai = tau[0] * di + tau[1] * dr;
-    for (int i = 0; i < len; ++i) {
-        const double vr = v[2 * i], vi = v[2 * i + 1];
-        z[2 * i] -= ar * vr - ai * vi;
-        z[2 * i + 1] -= ar * vi + ai * vr;
-    }
-}
-
 // Forward pass with a checkpoint of rows [sbot+1, n) at the start of every
 // block, stored row-major (row-contiguous across columns):
-//   ck[(cb_t + r - sbot_t - 1) * nev + c],  cb_t = sum_{t' < t} (n - sbot_t' - 1)
-// (complex: E = 2 interleaved doubles per entry, every index times E).
-template <bool C>
+//   ck[(cb_t + r - sbot_t - 1) * nev + c],  cb_t = sum_{t' < t} (n - sbot_t' - 1).
 __global__ __launch_bounds__(64) void k_adj_stream_fwd(int64_t n, int nbw, int64_t nev,
                                                        const double* __restrict__ hv,
                                                        const double* __restrict__ ht,
                                                        double* __restrict__ Z, int64_t ldz,
                                                        double* __restrict__ ck)
 {
-    constexpr int E = C ? 2 : 1;
     const int64_t c = (int64_t)blockIdx.x * 64 + threadIdx.x;
     if (c >= nev) return;
-    double* z = Z + c * ldz * E;
+    double* z = Z + c * ldz;
     const int64_t nblk = (n - 2 + KB - 1) / KB;
     int64_t cb = 0;
     for (int64_t t = 0; t < nblk; ++t) {
         const int64_t rlo = blk_sbot(n, t) + 1;
-        for (int64_t r = rlo; r < n; ++r)
-            for (int q = 0; q < E; ++q) ck[((cb + r - rlo) * nev + c) * E + q] = z[r * E + q];
+        for (int64_t r = rlo; r < n; ++r) ck[(cb + r - rlo) * nev + c] = z[r];
         cb += n - rlo;
         for_block_forward(n, nbw, t, [&](int64_t k, int64_t r0, int len) {
-            if constexpr (C) apply_cplx(z + r0 * E, hv + k * nbw * E, ht + k * E, len);
-            else apply_real(z + r0, hv + k * nbw, ht[k], len);
+            apply_real(z + r0, hv + k * nbw, ht[k], len);
         });
     }
 }
@@ -618,10 +595,6 @@ constexpr int RCH = 32;   // dv entries reduced per LDS round
 // the wave's 64 column contributions to dv (entries 0..len-1) and dtau
 // (entry len) are summed through LDS and written as this wave's partial:
 //   part[(wave * K + k) * (nbw + 1) + e]   (dtau at e = nbw).
-// Complex (conjugate-Wirtinger gradients, w = v^H z, gamma = v^H g):
-//   dv += -conj(tau) conj(w) g - tau conj(gamma) z,  dtau += -conj(w) gamma,
-//   g <- g - conj(tau) gamma v;  every index times E = 2.
-template <bool C>
 __global__ __launch_bounds__(64) void k_adj_stream_bwd(int64_t n, int nbw, int64_t nev,
                                                        const double* __restrict__ hv,
                                                        const double* __restrict__ ht,
@@ -631,15 +604,13 @@ __global__ __launch_bounds__(64) void k_adj_stream_bwd(int64_t n, int nbw, int64
                                                        double* __restrict__ G, int64_t ldg,
                                                        double* __restrict__ part, int64_t K)
 {
-    constexpr int E = C ? 2 : 1;
-    constexpr int RC = RCH / E;   // entries per LDS round
     __shared__ double red[64][RCH + 1];
     const int tid = threadIdx.x;
     const int64_t c = (int64_t)blockIdx.x * 64 + tid;
     const bool valid = c < nev;
     const int64_t cc = valid ? c : 0;
-    double* z = Zs + cc * n * E;
-    double* g = G + cc * ldg * E;
+    double* z = Zs + cc * n;
+    double* g = G + cc * ldg;
     const int64_t nblk = (n - 2 + KB - 1) / KB;
     int64_t cb = 0;
     for (int64_t t = 0; t < nblk; ++t) cb += n - blk_sbot(n, t) - 1;
@@ -648,74 +619,17 @@ __global__ __launch_bounds__(64) void k_adj_stream_bwd(int64_t n, int nbw, int64
         cb -= n - rlo;
         int64_t pos = 0;
         if (valid) {
-            for (int64_t r = rlo; r < n; ++r)
-                for (int q = 0; q < E; ++q) z[r * E + q] = ck[((cb + r - rlo) * nev + c) * E + q];
+            for (int64_t r = rlo; r < n; ++r) z[r] = ck[(cb + r - rlo) * nev + c];
             for_block_forward(n, nbw, t, [&](int64_t k, int64_t r0, int len) {
-                for (int i = 0; i < len; ++i)
-                    for (int q = 0; q < E; ++q)
-                        tape[((pos + i) * nev + c) * E + q] = z[(r0 + i) * E + q];
+                for (int i = 0; i < len; ++i) tape[(pos + i) * nev + c] = z[r0 + i];
                 pos += len;
-                if constexpr (C) apply_cplx(z + r0 * E, hv + k * nbw * E, ht + k * E, len);
-                else apply_real(z + r0, hv + k * nbw, ht[k], len);
+                apply_real(z + r0, hv + k * nbw, ht[k], len);
             });
         } else {
             for_block_forward(n, nbw, t, [&](int64_t, int64_t, int len) { pos += len; });
         }
         for_block_reverse(n, nbw, t, [&](int64_t k, int64_t r0, int len) {
             pos -= len;
-            if constexpr (C) {
-                const double* v = hv + k * nbw * 2;
-                const double tr = ht[2 * k], ti = ht[2 * k + 1];
-                double gr = 0.0, gi = 0.0, wr = 0.0, wi = 0.0;   // gamma = v^H g, w = v^H z
-                if (valid)
-                    for (int i = 0; i < len; ++i) {
-                        const double vr = v[2 * i], vi = v[2 * i + 1];
-                        const double xr = g[(r0 + i) * 2], xi = g[(r0 + i) * 2 + 1];
-                        const double* zp = &tape[((pos + i) * nev + c) * 2];
-                        gr = fma(vr, xr, fma(vi, xi, gr));
-                        gi = fma(vr, xi, fma(-vi, xr, gi));
-                        wr = fma(vr, zp[0], fma(vi, zp[1], wr));
-                        wi = fma(vr, zp[1], fma(-vi, zp[0], wi));
-                    }
-                // a = -conj(tau) conj(w), b = -tau conj(gamma)
-                const double ar = -(tr * wr - ti * wi), ai = -(-tr * wi - ti * wr);
-                const double br = -(tr * gr + ti * gi), bi = -(ti * gr - tr * gi);
-                for (int e0 = 0; e0 <= len; e0 += RC) {
-                    for (int i = 0; i < RC; ++i) {
-                        const int e = e0 + i;
-                        double vr = 0.0, vi = 0.0;
-                        if (valid && e < len) {
-                            const double xr = g[(r0 + e) * 2], xi = g[(r0 + e) * 2 + 1];
-                            const double* zp = &tape[((pos + e) * nev + c) * 2];
-                            vr = ar * xr - ai * xi + br * zp[0] - bi * zp[1];
-                            vi = ar * xi + ai * xr + br * zp[1] + bi * zp[0];
-                        } else if (valid && e == len) {   // -conj(w) gamma
-                            vr = -(wr * gr + wi * gi);
-                            vi = -(wr * gi - wi * gr);
-                        }
-                        red[tid][2 * i] = vr;
-                        red[tid][2 * i + 1] = vi;
-                    }
-                    __syncthreads();
-                    if (tid < RCH && e0 + tid / 2 <= len) {
-                        double s = 0.0;
-                        for (int l = 0; l < 64; ++l) s += red[l][tid];
-                        const int e = e0 + tid / 2;
-                        part[(((int64_t)blockIdx.x * K + k) * (nbw + 1) + (e < len ? e : nbw)) * 2 +
-                             (tid & 1)] = s;
-                    }
-                    __syncthreads();
-                }
-                if (valid) {   // g <- g - conj(tau) gamma v
-                    const double fr = tr * gr + ti * gi, fi = tr * gi - ti * gr;
-                    for (int i = 0; i < len; ++i) {
-                        const double vr = v[2 * i], vi = v[2 * i + 1];
-                        g[(r0 + i) * 2] -= fr * vr - fi * vi;
-                        g[(r0 + i) * 2 + 1] -= fr * vi + fi * vr;
-                    }
-                }
-                return;
-            }
             const double* v = hv + k * nbw;
             const double tau = ht[k];
             double gk = 0.0, wk = 0.0;
@@ -749,9 +663,7 @@ __global__ __launch_bounds__(64) void k_adj_stream_bwd(int64_t n, int nbw, int64
     }
 }
 
-// dv, dtau = sums of the waves' partials in wave order (complex: per
-// component).
-template <bool C>
+// dv, dtau = sums of the waves' partials in wave order.
 __global__ __launch_bounds__(256) void k_adj_stream_finish(int64_t n, int nbw, int64_t K,
                                                            int64_t nwaves,
                                                            const double* __restrict__ part,
@@ -771,17 +683,14 @@ __global__ __launch_bounds__(256) void k_adj_stream_finish(int64_t n, int nbw, i
     const int64_t j = k - stage_offset(n, nbw, lo);
     const int64_t r0 = lo + 1 + j * nbw;
     const int len = (int)(n - r0 < nbw ? n - r0 : nbw);
-    constexpr int E = C ? 2 : 1;
-    for (int q = 0; q < E; ++q) {
-        if (e < nbw && e >= len) {
-            dv[(k * nbw + e) * E + q] = 0.0;
-            continue;
-        }
-        double s = 0.0;
-        for (int64_t w = 0; w < nwaves; ++w) s += part[((w * K + k) * (nbw + 1) + e) * E + q];
-        if (e == nbw) dtau[k * E + q] = s;
-        else dv[(k * nbw + e) * E + q] = s;
+    if (e < nbw && e >= len) {
+        dv[k * nbw + e] = 0.0;
+        return;
     }
+    double s = 0.0;
+    for (int64_t w = 0; w < nwaves; ++w) s += part[(w * K + k) * (nbw + 1) + e];
+    if (e == nbw) dtau[k] = s;
+    else dv[k * nbw + e] = s;
 }
 
 __global__ void k_fill_zero(double* p, int64_t count)
@@ -814,15 +723,13 @@ int adj_apb(int nbw)
     }
 }
 
-// complex problems always take the streaming form
-AdjLayout adj_layout(int64_t n, int nbw, int64_t nev, bool cplx = false)
+AdjLayout adj_layout(int64_t n, int nbw, int64_t nev)
 {
     AdjLayout L;
-    const size_t el = cplx ? 2 * sizeof(double) : sizeof(double);
     size_t off = HDR_BYTES;
     L.zs = off;
-    off = al(off + (size_t)n * nev * el);
-    if (!cplx && use_blocked(n, nbw, false)) {
+    off = al(off + (size_t)n * nev * sizeof(double));
+    if (use_blocked(n, nbw, false)) {
         const int nt = adj_tiles(nbw);
         L.nblocks = blocked_num_blocks(n, nbw);
         L.nstrips = (nev + 15) / 16;
@@ -848,11 +755,11 @@ AdjLayout adj_layout(int64_t n, int nbw, int64_t nev, bool cplx = false)
         }
         L.nwaves = (nev + 63) / 64;
         L.ckpt = off;
-        off = al(off + (size_t)ckrows * nev * el);
+        off = al(off + (size_t)ckrows * nev * sizeof(double));
         L.tape = off;
-        off = al(off + (size_t)taperows * nev * el);
+        off = al(off + (size_t)taperows * nev * sizeof(double));
         L.part = off;
-        off = al(off + (size_t)L.nwaves * num_reflectors(n, nbw) * (nbw + 1) * el);
+        off = al(off + (size_t)L.nwaves * num_reflectors(n, nbw) * (nbw + 1) * sizeof(double));
     }
     L.total = off;
     return L;
@@ -944,29 +851,9 @@ int adj_forward(int64_t n, int nbw, int64_t nev, const double* hv, const double*
             default: return TRBT_ERR_INTERNAL;
         }
     } else {
-        hipLaunchKernelGGL(k_adj_stream_fwd<false>, dim3((unsigned)L.nwaves), dim3(64), 0, st, n,
-                           nbw, nev, hv, ht, Z, ldz, (double*)(ws + L.ckpt));
+        hipLaunchKernelGGL(k_adj_stream_fwd, dim3((unsigned)L.nwaves), dim3(64), 0, st, n, nbw,
+                           nev, hv, ht, Z, ldz, (double*)(ws + L.ckpt));
     }
-    return hipGetLastError() == hipSuccess ? TRBT_SUCCESS : TRBT_ERR_HIP;
-}
-
-// streaming form only (the complex adjoint): forward with checkpoints, then
-// the reverse sweep and the wave-order sums
-template <bool C>
-int stream_both(int64_t n, int nbw, int64_t nev, const double* hv, const double* ht, double* Z,
-                int64_t ldz, double* G, int64_t ldg, double* dv, double* dtau, char* ws,
-                const AdjLayout& L, hipStream_t st)
-{
-    const int64_t K = num_reflectors(n, nbw);
-    const unsigned nw = (unsigned)L.nwaves;
-    hipLaunchKernelGGL(k_adj_stream_fwd<C>, dim3(nw), dim3(64), 0, st, n, nbw, nev, hv, ht, Z,
-                       ldz, (double*)(ws + L.ckpt));
-    hipLaunchKernelGGL(k_adj_stream_bwd<C>, dim3(nw), dim3(64), 0, st, n, nbw, nev, hv, ht,
-                       (double*)(ws + L.zs), (const double*)(ws + L.ckpt), (double*)(ws + L.tape),
-                       G, ldg, (double*)(ws + L.part), K);
-    const int64_t cnt = K * (nbw + 1);
-    hipLaunchKernelGGL(k_adj_stream_finish<C>, dim3((unsigned)((cnt + 255) / 256)), dim3(256), 0,
-                       st, n, nbw, K, L.nwaves, (const double*)(ws + L.part), dv, dtau);
     return hipGetLastError() == hipSuccess ? TRBT_SUCCESS : TRBT_ERR_HIP;
 }
 
@@ -985,13 +872,12 @@ int adj_backward(int64_t n, int nbw, int64_t nev, const double* hv, const double
     } else {
         const int64_t K = num_reflectors(n, nbw);
         const unsigned nw = (unsigned)L.nwaves;
-        hipLaunchKernelGGL(k_adj_stream_bwd<false>, dim3(nw), dim3(64), 0, st, n, nbw, nev, hv, ht,
+        hipLaunchKernelGGL(k_adj_stream_bwd, dim3(nw), dim3(64), 0, st, n, nbw, nev, hv, ht,
                            (double*)(ws + L.zs), (const double*)(ws + L.ckpt),
                            (double*)(ws + L.tape), G, ldg, (double*)(ws + L.part), K);
         const int64_t cnt = K * (nbw + 1);
-        hipLaunchKernelGGL(k_adj_stream_finish<false>, dim3((unsigned)((cnt + 255) / 256)),
-                           dim3(256), 0, st, n, nbw, K, L.nwaves, (const double*)(ws + L.part),
-                           dv, dtau);
+        hipLaunchKernelGGL(k_adj_stream_finish, dim3((unsigned)((cnt + 255) / 256)), dim3(256), 0,
+                           st, n, nbw, K, L.nwaves, (const double*)(ws + L.part), dv, dtau);
     }
     return hipGetLastError() == hipSuccess ? TRBT_SUCCESS : TRBT_ERR_HIP;
 }
@@ -1007,52 +893,6 @@ int zero_grads(int64_t K, int nbw, double* dv, double* dtau, hipStream_t st)
 }  // namespace
 
 extern "C" {
-
-int trbt_adjoint_workspace_bytes_z(int64_t n, int nbw, int64_t nev, int ckpt_every,
-                                   size_t* bytes)
-{
-    if (n < 0) return -1;
-    if (nbw < 1 || nbw > TRBT_NBW_MAX) return -2;
-    if (nev < 0 || nev > n) return -3;
-    if (ckpt_every != 0 && ckpt_every != 16) return -4;
-    if (!bytes) return -5;
-    *bytes = (num_reflectors(n, nbw) > 0 && nev > 0) ? adj_layout(n, nbw, nev, true).total : 0;
-    return TRBT_SUCCESS;
-}
-
-int trans_ev_tridi_to_band_adjoint_z(int64_t n, int nbw, int64_t nev, const trbt_z* hh_v,
-                                     const trbt_z* hh_tau, const trbt_z* Z_in, int64_t ldz,
-                                     trbt_z* G, int64_t ldg, trbt_z* dv, trbt_z* dtau,
-                                     int ckpt_every, void* work, size_t work_bytes,
-                                     void* stream)
-{
-    int rc = adj_validate(n, nbw, nev, (const double*)hh_v, (const double*)hh_tau,
-                          (const double*)Z_in, ldz, (const double*)G, ldg, (const double*)dv,
-                          (const double*)dtau, ckpt_every, work, work_bytes);
-    if (rc) return rc;
-    const int64_t K = num_reflectors(n, nbw);
-    if (K == 0) return TRBT_SUCCESS;   // dL/dZ_in = G, nothing else to write
-    rc = check_device();
-    if (rc) return rc;
-    hipStream_t st = (hipStream_t)stream;
-    if (nev == 0) {   // zero parameter gradients (interleaved complex: 2 doubles each)
-        hipLaunchKernelGGL(k_fill_zero, dim3((unsigned)((2 * K * nbw + 255) / 256)), dim3(256), 0,
-                           st, (double*)dv, 2 * K * nbw);
-        hipLaunchKernelGGL(k_fill_zero, dim3((unsigned)((2 * K + 255) / 256)), dim3(256), 0, st,
-                           (double*)dtau, 2 * K);
-        return hipGetLastError() == hipSuccess ? TRBT_SUCCESS : TRBT_ERR_HIP;
-    }
-    const AdjLayout L = adj_layout(n, nbw, nev, true);
-    if (!work || work_bytes < L.total) return TRBT_ERR_WORKSPACE;
-    char* ws = (char*)work;
-    double* Zs = (double*)(ws + L.zs);
-    if (hipMemcpy2DAsync(Zs, (size_t)n * sizeof(trbt_z), Z_in, (size_t)ldz * sizeof(trbt_z),
-                         (size_t)n * sizeof(trbt_z), (size_t)nev, hipMemcpyDeviceToDevice,
-                         st) != hipSuccess)
-        return TRBT_ERR_HIP;
-    return stream_both<true>(n, nbw, nev, (const double*)hh_v, (const double*)hh_tau, Zs, n,
-                             (double*)G, ldg, (double*)dv, (double*)dtau, ws, L, st);
-}
 
 int trbt_adjoint_workspace_bytes_d(int64_t n, int nbw, int64_t nev, int ckpt_every,
                                    size_t* bytes)
