@@ -361,7 +361,7 @@ def adjoint_complex_leg(warmup: int, plain: bool = True):
     log(f"C5 complex forward + one-call adjoint: {ms:.1f} ms")
     flops = 4 * 18 * L * nev
     out = {
-        "workload": "C5 complex: n=4096, nbw=64, nev=2048, forward + adjoint (streaming form), "
+        "workload": "C5 complex: n=4096, nbw=64, nev=2048, forward + adjoint (stage-parallel form), "
                     "G seed 2005",
         "flops_counted": flops, "ours_ms": round(ms, 2),
         "ours_tflops": round(flops / ms / 1e9, 4),
