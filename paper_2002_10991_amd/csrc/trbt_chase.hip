@@ -225,6 +225,12 @@ __global__ __launch_bounds__(64 * NW) void k_chase(int64_t n, int b,
         const int64_t S = sweeps_in_stage(n, b, s);
         const int64_t Sp = s > 0 ? sweeps_in_stage(n, b, s - 1) : 0;
         int64_t kref = stage_offset(n, b, s);
+        // the previous step's right block, kept in registers: it is exactly
+        // this step's column c and left block (rows [r0, r0+len), columns
+        // c .. c+b-1, dealt over the waves by column offset like the right
+        // block), and no other step touches it in between (the one shared
+        // entry, its last, was finished in the previous step's tail)
+        cx car[COLS];
         for (int64_t j = 0; j < S; ++j, ++kref) {
             if (s > 0) {   // (s-1, 0 .. j+1) done
                 if (threadIdx.x == 0) {
@@ -239,22 +245,26 @@ __global__ __launch_bounds__(64 * NW) void k_chase(int64_t n, int b,
             const int64_t rest = n - r0 - len;
             const int nr = (int)(rest < b ? rest : b);          // right-block rows
             const int64_t c = j == 0 ? s : r0 - b;
-            const int nl = j == 0 ? 0 : b - 1;                  // left-block columns c+1 ..
+            const bool has_next = j + 1 < S;                    // else the right block is stored here
             // the right block's last entry (row r0+2b-1, column r0+b-1) is
             // the leading entry of the column step (s-1, j+2) annihilates:
             // its row is finished in the tail, after that step
             const bool corner = len == b && nr == b;
             const bool crow = corner && lane == b - 1;          // this lane holds that row
 
-            // 1. loads
+            // 1. loads (column c + m, m = w + NW t: x for m = 0, the left
+            // block for m >= 1 -- carried over for j > 0)
             cx x = {0.0, 0.0};
-            if (w == 0 && lane < len) x = ldx<C>(at(r0 + lane, c));
+            if (w == 0) {
+                if (j > 0) x = car[0];
+                else if (lane < len) x = ldx<C>(at(r0 + lane, c));
+            }
             cx yl[COLS], yr[COLS], ad[COLS];
 #pragma unroll
             for (int t = 0; t < COLS; ++t) {
                 const int m = w + NW * t;
-                yl[t] = yr[t] = ad[t] = cx{0.0, 0.0};
-                if (m < nl && lane < len) yl[t] = ldx<C>(at(r0 + lane, c + 1 + m));
+                yr[t] = ad[t] = cx{0.0, 0.0};
+                yl[t] = (j > 0 && m >= 1) ? car[t] : cx{0.0, 0.0};
                 // (the corner is read in the tail: step (s-1, j+2) may be
                 // writing it now)
                 if (m < len && lane < nr && !(crow && m == b - 1))
@@ -314,10 +324,10 @@ __global__ __launch_bounds__(64 * NW) void k_chase(int64_t n, int b,
 #pragma unroll
                 for (int t = 0; t < COLS; ++t) {
                     const int m = w + NW * t;
-                    if (m < nl) {
+                    if (j > 0 && m >= 1 && m < b) {
                         const cx f = cmulc<C>(tau, dot[t]);           // conj(tau) (v^H y)
                         yl[t] = csub<C>(yl[t], cmul<C>(f, vi));
-                        if (lane < len) stx<C>(at(r0 + lane, c + 1 + m), yl[t]);
+                        if (lane < len) stx<C>(at(r0 + lane, c + m), yl[t]);
                     }
                 }
             }
@@ -354,7 +364,7 @@ __global__ __launch_bounds__(64 * NW) void k_chase(int64_t n, int b,
                     const cx vm = ldx<C>(&vs[m * E]);
                     if (!crow) {
                         yr[t] = csub<C>(yr[t], cmul_cb<C>(tz, vm));
-                        if (lane < nr) stx<C>(at(r0 + len + lane, r0 + m), yr[t]);
+                        if (!has_next && lane < nr) stx<C>(at(r0 + len + lane, r0 + m), yr[t]);
                     }
                     const cx wm = shfl_x<C>(wv, m);
                     ad[t] = csub<C>(ad[t], cadd<C>(cmul_cb<C>(wv, vm), cmul_cb<C>(vi, wm)));
@@ -392,10 +402,12 @@ __global__ __launch_bounds__(64 * NW) void k_chase(int64_t n, int b,
                     const int m = w + NW * t;
                     if (m < len && crow) {
                         yr[t] = csub<C>(yr[t], cmul_cb<C>(tzc, ldx<C>(&vs[m * E])));
-                        stx<C>(at(r0 + len + lane, r0 + m), yr[t]);
+                        if (!has_next) stx<C>(at(r0 + len + lane, r0 + m), yr[t]);
                     }
                 }
             }
+#pragma unroll
+            for (int t = 0; t < COLS; ++t) car[t] = yr[t];
 
             // publish the step: every wave waits until its stores have
             // reached L2, then one agent-scope release (one write-back of
