@@ -38,6 +38,7 @@ namespace {
 constexpr int ZC = 256;    // columns per workgroup (one per thread)
 constexpr int ZSEG = 16;   // stages per checkpointed segment
 constexpr int ZR = 16;     // gradient entries per LDS reduction round
+constexpr int ZL = 16;     // rows loaded together (loads in flight per thread)
 
 __host__ __device__ inline int64_t zseg_lo(int64_t n, int64_t t)   // lowest stage of segment t
 {
@@ -110,25 +111,57 @@ __global__ __launch_bounds__(ZC) void k_zstage_fwd(int64_t n, int nbw, int64_t n
     const int64_t k = stage_offset(n, nbw, s) + j;
     const double* v = hv + k * nbw * 2;
     if (c >= nev) return;
+    // rows are read ZL at a time, all loads issued before any is used
     double dr = 0.0, di = 0.0;   // v^H z
-    for (int i = 0; i < len; ++i) {
-        const double* zp = &W[((r0 + i) * nev + c) * 2];
-        const double zr = zp[0], zi = zp[1], vr = v[2 * i], vi = v[2 * i + 1];
-        if (tape) {
-            double* tp = &tape[((r0 + i - s - 1) * nev + c) * 2];
-            tp[0] = zr;
-            tp[1] = zi;
+    for (int i0 = 0; i0 < len; i0 += ZL) {
+        double zr[ZL], zi[ZL];
+#pragma unroll
+        for (int q = 0; q < ZL; ++q) {
+            zr[q] = zi[q] = 0.0;
+            if (i0 + q < len) {
+                const double* zp = &W[((r0 + i0 + q) * nev + c) * 2];
+                zr[q] = zp[0];
+                zi[q] = zp[1];
+            }
         }
-        dr = fma(vr, zr, fma(vi, zi, dr));
-        di = fma(vr, zi, fma(-vi, zr, di));
+#pragma unroll
+        for (int q = 0; q < ZL; ++q) {
+            if (i0 + q < len) {
+                const int i = i0 + q;
+                if (tape) {
+                    double* tp = &tape[((r0 + i - s - 1) * nev + c) * 2];
+                    tp[0] = zr[q];
+                    tp[1] = zi[q];
+                }
+                const double vr = v[2 * i], vi = v[2 * i + 1];
+                dr = fma(vr, zr[q], fma(vi, zi[q], dr));
+                di = fma(vr, zi[q], fma(-vi, zr[q], di));
+            }
+        }
     }
     const double tr = ht[2 * k], ti = ht[2 * k + 1];
     const double ar = tr * dr - ti * di, ai = tr * di + ti * dr;   // tau (v^H z)
-    for (int i = 0; i < len; ++i) {
-        double* zp = &W[((r0 + i) * nev + c) * 2];
-        const double vr = v[2 * i], vi = v[2 * i + 1];
-        zp[0] -= ar * vr - ai * vi;
-        zp[1] -= ar * vi + ai * vr;
+    for (int i0 = 0; i0 < len; i0 += ZL) {
+        double zr[ZL], zi[ZL];
+#pragma unroll
+        for (int q = 0; q < ZL; ++q) {
+            zr[q] = zi[q] = 0.0;
+            if (i0 + q < len) {
+                const double* zp = &W[((r0 + i0 + q) * nev + c) * 2];
+                zr[q] = zp[0];
+                zi[q] = zp[1];
+            }
+        }
+#pragma unroll
+        for (int q = 0; q < ZL; ++q) {
+            if (i0 + q < len) {
+                const int i = i0 + q;
+                double* zp = &W[((r0 + i) * nev + c) * 2];
+                const double vr = v[2 * i], vi = v[2 * i + 1];
+                zp[0] = zr[q] - (ar * vr - ai * vi);
+                zp[1] = zi[q] - (ar * vi + ai * vr);
+            }
+        }
     }
 }
 
@@ -158,27 +191,63 @@ __global__ __launch_bounds__(ZC) void k_zstage_bwd(int64_t n, int nbw, int64_t n
     auto zp = [&](int i) { return &tape[((r0 + i - s - 1) * nev + cc) * 2]; };
     double gr = 0.0, gi = 0.0, wr = 0.0, wi = 0.0;   // gamma = v^H g, w = v^H z
     if (valid)
-        for (int i = 0; i < len; ++i) {
-            const double vr = v[2 * i], vi = v[2 * i + 1];
-            const double* x = gp(i);
-            const double* z = zp(i);
-            gr = fma(vr, x[0], fma(vi, x[1], gr));
-            gi = fma(vr, x[1], fma(-vi, x[0], gi));
-            wr = fma(vr, z[0], fma(vi, z[1], wr));
-            wi = fma(vr, z[1], fma(-vi, z[0], wi));
+        for (int i0 = 0; i0 < len; i0 += ZL) {   // ZL rows of g and z in flight
+            double xr[ZL], xi[ZL], yr[ZL], yi[ZL];
+#pragma unroll
+            for (int q = 0; q < ZL; ++q) {
+                xr[q] = xi[q] = yr[q] = yi[q] = 0.0;
+                if (i0 + q < len) {
+                    const double* x = gp(i0 + q);
+                    const double* z = zp(i0 + q);
+                    xr[q] = x[0];
+                    xi[q] = x[1];
+                    yr[q] = z[0];
+                    yi[q] = z[1];
+                }
+            }
+#pragma unroll
+            for (int q = 0; q < ZL; ++q) {
+                if (i0 + q < len) {
+                    const double vr = v[2 * (i0 + q)], vi = v[2 * (i0 + q) + 1];
+                    gr = fma(vr, xr[q], fma(vi, xi[q], gr));
+                    gi = fma(vr, xi[q], fma(-vi, xr[q], gi));
+                    wr = fma(vr, yr[q], fma(vi, yi[q], wr));
+                    wi = fma(vr, yi[q], fma(-vi, yr[q], wi));
+                }
+            }
         }
     // a = -conj(tau) conj(w), b = -tau conj(gamma)
     const double ar = -(tr * wr - ti * wi), ai = -(-tr * wi - ti * wr);
     const double br = -(tr * gr + ti * gi), bi = -(ti * gr - tr * gi);
+    const double fr = tr * gr + ti * gi, fi = tr * gi - ti * gr;   // conj(tau) gamma
     for (int e0 = 0; e0 <= len; e0 += ZR) {
+        // this round's rows of g and z (loads issued together); the
+        // contributions use the incoming g, which is then updated in place:
+        // g <- g - conj(tau) gamma v
+        double xr[ZR], xi[ZR], yr[ZR], yi[ZR];
+#pragma unroll
+        for (int q = 0; q < ZR; ++q) {
+            xr[q] = xi[q] = yr[q] = yi[q] = 0.0;
+            if (valid && e0 + q < len) {
+                const double* x = gp(e0 + q);
+                const double* z = zp(e0 + q);
+                xr[q] = x[0];
+                xi[q] = x[1];
+                yr[q] = z[0];
+                yi[q] = z[1];
+            }
+        }
+#pragma unroll
         for (int q = 0; q < ZR; ++q) {
             const int e = e0 + q;
             double vr = 0.0, vi = 0.0;
             if (valid && e < len) {
-                const double* x = gp(e);
-                const double* z = zp(e);
-                vr = ar * x[0] - ai * x[1] + br * z[0] - bi * z[1];
-                vi = ar * x[1] + ai * x[0] + br * z[1] + bi * z[0];
+                vr = ar * xr[q] - ai * xi[q] + br * yr[q] - bi * yi[q];
+                vi = ar * xi[q] + ai * xr[q] + br * yi[q] + bi * yr[q];
+                const double wvr = v[2 * e], wvi = v[2 * e + 1];
+                double* x = gp(e);
+                x[0] = xr[q] - (fr * wvr - fi * wvi);
+                x[1] = xi[q] - (fr * wvi + fi * wvr);
             } else if (valid && e == len) {   // -conj(w) gamma
                 vr = -(wr * gr + wi * gi);
                 vi = -(wr * gi - wi * gr);
@@ -194,15 +263,6 @@ __global__ __launch_bounds__(ZC) void k_zstage_bwd(int64_t n, int nbw, int64_t n
             part[((chunk * K + k) * (nbw + 1) + (e < len ? e : nbw)) * 2 + (tid & 1)] = acc;
         }
         __syncthreads();
-    }
-    if (valid) {   // g <- g - conj(tau) gamma v
-        const double fr = tr * gr + ti * gi, fi = tr * gi - ti * gr;
-        for (int i = 0; i < len; ++i) {
-            double* x = gp(i);
-            const double vr = v[2 * i], vi = v[2 * i + 1];
-            x[0] -= fr * vr - fi * vi;
-            x[1] -= fr * vi + fi * vr;
-        }
     }
 }
 
