@@ -23,20 +23,32 @@
 // Parallel schedule (the pipelined stages of Sec. 2.2.1's bulge chasing).
 // In the sequential order every step of stage s-1 precedes every step of
 // stage s.  The footprint of (s, j) meets those of stage s-1 only for steps
-// j' <= j+2 and never meets stage s-2 beyond what stage s-1 already waited
-// for, so (s, j) may run as soon as (s-1, 0 .. j+2) are done: stages form a
-// pipeline three steps apart.  Each stage is run start to finish by one
-// workgroup (stages are dealt in increasing order from a ticket counter),
-// which publishes its progress after every step with an agent-scope release
-// and waits for its predecessor's with an agent-scope acquire.  A stage only
-// ever waits on a stage whose ticket was taken earlier by a workgroup that is
-// running, so the wait always ends; it is bounded anyway (a wall-clock limit
-// that sets an error flag and makes every workgroup leave).
+// j' <= j+2, and its overlap with (s-1, j+2) is one entry: the right block's
+// last, which is the leading entry of the column (s-1, j+2) annihilates.  So
+// (s, j) runs once (s-1, 0 .. j+1) are done, leaves the last row of its
+// right block for a tail that waits for (s-1, j+2), and finishes it with the
+// corner's new value; stages form a pipeline two steps apart.  (Exhaustive
+// checks of this schedule against the traced sequential footprints, over
+// stage distances 1-5 and ragged ends, find no other overlap.)  Each stage is
+// run start to finish by one workgroup (stages are dealt in increasing order
+// from a ticket counter), which publishes its progress after every step with
+// an agent-scope release and waits for its predecessor's with an agent-scope
+// acquire.  A stage only ever waits on a stage whose ticket was taken earlier
+// by a workgroup that is running, so the wait always ends; it is bounded
+// anyway (a wall-clock limit that sets an error flag and makes every
+// workgroup leave).
 //
-// One step on one workgroup of four waves, lane = row of the block:
-//   1. all waves load their columns of the left, right and diagonal blocks
-//      (columns dealt round-robin over the waves); the diagonal block is also
-//      mirrored into LDS as a dense Hermitian matrix; wave 0 loads column c;
+// A step's right block is exactly the next step's column c and left block,
+// and no other step touches it in between, so it stays in registers and is
+// stored once, by the next step.
+//
+// One step on one workgroup of 16 waves, lane = row of the block, block
+// columns dealt round-robin over the waves by their offset (from c for the
+// left block, from r0 for the others):
+//   1. all waves load their columns of the right and diagonal blocks (the
+//      left block and column c come from the registers of the previous
+//      step, or column c from memory for j = 0); the diagonal block is also
+//      mirrored into LDS as a dense Hermitian matrix;
 //   2. wave 0 builds the reflector (one wave-wide sum of squares), writes
 //      (v, tau) and the annihilated column;
 //   3. left block: y <- y - conj(tau) v (v^H y) per column (wave-wide sums,
