@@ -244,7 +244,9 @@ __global__ __launch_bounds__(64 * NW) void k_chase(int64_t n, int b,
         // entry, its last, was finished in the previous step's tail)
         cx car[COLS];
         for (int64_t j = 0; j < S; ++j, ++kref) {
-            if (s > 0) {   // (s-1, 0 .. j+1) done
+            // (s-1, 0 .. j+1) done: for j > 0 the previous step's tail already
+            // waited for that
+            if (s > 0 && j == 0) {
                 if (threadIdx.x == 0) {
                     fail_sh = !chase_wait(&prog[s - 1], (int)(j + 2 < Sp ? j + 2 : Sp), ctl);
                     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
@@ -384,11 +386,13 @@ __global__ __launch_bounds__(64 * NW) void k_chase(int64_t n, int b,
                 }
             }
 
-            // tail: (s-1, 0 .. j+2) done; with the corner, the last row of
-            // the right block: z[b-1] completed with the corner's current
-            // value, then that row's update.  Every step waits, so that a
-            // finished (s, j) implies a finished (s-1, j+2).
-            if (s > 0 && j + 2 < Sp) {
+            // tail: (s-1, 0 .. j+2) done (all of stage s-1 when it has no
+            // step j+2); with the corner, the last row of the right block:
+            // z[b-1] completed with the corner's current value, then that
+            // row's update.  Every step waits, so that a finished (s, j)
+            // implies a finished (s-1, j+2), and the next step needs no wait
+            // of its own.
+            if (s > 0) {
                 if (threadIdx.x == 0) {
                     fail_sh = !chase_wait(&prog[s - 1], (int)(j + 3 < Sp ? j + 3 : Sp), ctl);
                     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
