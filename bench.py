@@ -471,6 +471,68 @@ def chase_leg(steps: int, warmup: int, cpu: bool = True):
     return res
 
 
+def tridiag_leg(steps: int, warmup: int, cpu: bool = True):
+    """The lowest nev eigenpairs of the tridiagonal T that the GPU chase makes
+    of the n = 8192 real and n = 32768 complex workloads' bands, by bisection and
+    inverse iteration on the GPU (complex: Re e with the last entry |e[n-2]|);
+    the oracle's implicit QL (all eigenpairs,
+    O(n^3)) timed on an n = 1024 sample and scaled by n^3."""
+    import torch
+    import synth
+    import paper_2002_10991_amd as T
+    dev = torch.device("cuda:0")
+    stream = torch.cuda.current_stream()
+    res = {}
+    for label, n, nev, dt, seed, shift in (("C2", 8192, 4096, "d", 1002, True),
+                                           ("C3", 32768, 8192, "z", 1003, False)):
+        ab = synth.band_matrix(n, 64, seed, dt, diag_shift=shift)
+        d, e, _, _ = T.band_to_tridiagonal(torch.from_numpy(np.ascontiguousarray(ab.T)).to(dev),
+                                           64)
+        if dt == "z":   # real betas except the last subdiagonal: T = D T_r D^H
+            er = e.real.clone()
+            er[-1] = e[-1].abs()
+            e = er
+        e = e.to(torch.float64).contiguous()
+        w = torch.empty(nev, dtype=torch.float64, device=dev)
+        zb = torch.empty((nev, n), dtype=torch.float64, device=dev)
+        nb = T.trbt_tridiag_eigh_workspace_bytes(n, nev)
+        buf = torch.empty(nb + T.TRBT_WORK_ALIGN, dtype=torch.uint8, device=dev)
+        work = buf[(-buf.data_ptr()) % T.TRBT_WORK_ALIGN:][:nb]
+
+        def run():
+            rc = T.trbt_tridiag_eigh_d(n, nev, d, e, w, zb, n, work, nb, stream)
+            if rc:
+                raise T.TrbtError(rc, "trbt_tridiag_eigh_d")
+
+        for _ in range(max(warmup, 1)):
+            run()
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        for _ in range(steps):
+            run()
+        e1.record(stream)
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1) / steps
+        r = {"n": n, "nev": nev, "ms": round(ms, 3),
+             "input": f"T from the GPU chase of the {label} band (nbw=64)"}
+        if cpu:
+            import oracle
+            ns = 1024
+            rng = np.random.default_rng(5)
+            t = time.perf_counter()
+            oracle.tridiagonal_eigh(rng.standard_normal(ns), rng.standard_normal(ns - 1))
+            cs = time.perf_counter() - t
+            est = cs * (n / ns) ** 3
+            r["cpu_oracle"] = {"sample": f"implicit QL, all eigenpairs, n={ns}; scaled by n^3",
+                               "sample_s": round(cs, 3), "extrapolated_s": round(est, 1),
+                               "cores": oracle.num_threads(), "kind": "oracle"}
+            r["speedup_vs_oracle"] = round(est / (ms / 1e3), 1)
+        log(f"tridiagonal eigenpairs {label}: {ms:.1f} ms")
+        res[label] = r
+    return res
+
+
 def committed_traffic(workload: str):
     """HBM bytes per launch of the apply kernel from the committed rocprofv3
     counter summary, if it was taken on the current kernel source; else None."""
@@ -506,6 +568,10 @@ def main():
                     help="skip the adjoint-vs-plain comparison on the differentiation workload")
     ap.add_argument("--adjoint-only", action="store_true",
                     help="run only the adjoint-vs-plain comparison and print its JSON")
+    ap.add_argument("--no-tridiag", action="store_true",
+                    help="skip the tridiagonal eigenpairs leg")
+    ap.add_argument("--tridiag-only", action="store_true",
+                    help="run only the tridiagonal eigenpairs leg and print its JSON")
     ap.add_argument("--no-chase", action="store_true",
                     help="skip the banded-to-tridiagonal bulge chasing leg")
     ap.add_argument("--chase-only", action="store_true",
@@ -538,6 +604,10 @@ def main():
         print(json.dumps({"batched_vs_loop": batched_leg(args.steps, args.warmup),
                           "batched_complex_vs_loop": batched_leg(args.steps, args.warmup, "z")}),
               flush=True)
+        return
+    if args.tridiag_only:
+        print(json.dumps({"tridiag": tridiag_leg(args.steps, args.warmup,
+                                                 not args.no_cpu_baseline)}), flush=True)
         return
     if args.chase_only:
         print(json.dumps({"chase": chase_leg(args.steps, args.warmup,
@@ -643,6 +713,8 @@ def main():
         out["adjoint_complex_vs_plain"] = adjoint_complex_leg(args.warmup, not args.no_plain)
     if not args.no_chase:
         out["chase"] = chase_leg(min(args.steps, 3), args.warmup, not args.no_cpu_baseline)
+    if not args.no_tridiag:
+        out["tridiag"] = tridiag_leg(min(args.steps, 3), args.warmup, not args.no_cpu_baseline)
     if not args.no_cpu_baseline:
         log("timing the CPU oracle on a column sample")
         out["cpu_baseline"] = cpu_baseline(cfg, V, tau, Z, L_total)

@@ -369,6 +369,36 @@ int trbt_band_to_tridi_z(int64_t n, int nbw, const trbt_z *ab, int64_t ldab, dou
                          trbt_z *e, trbt_z *hh_v, trbt_z *hh_tau, void *work,
                          size_t work_bytes, void *stream);
 
+/* ------------------------------------------------------------------------
+ * Tridiagonal eigenpairs (the step between the chase and the
+ * back-transformation, Eq. 2stage_solve): the lowest nev eigenvalues of the
+ * real symmetric tridiagonal T = diag(d) + subdiag(e), ascending, and their
+ * eigenvectors, computed only for the wanted ones -- eigenvalue i by
+ * bisection on the Sturm count, eigenvector i by inverse iteration (pivoted
+ * tridiagonal LU, a fixed pseudo-random start, three solves), one GPU thread
+ * per eigenpair.  Each eigenvector is normalised with its largest-magnitude
+ * entry positive.  Accuracy: residuals ||T z - w z|| ~ eps ||T||; the angle
+ * between the vectors of distinct eigenvalues ~ eps ||T|| / gap (no
+ * re-orthogonalisation among eigenvalues that agree to working precision).
+ * For the complex chase's T (every subdiagonal a real beta except e[n-2])
+ * pass Re e with its last entry replaced by |e[n-2]| and multiply the last
+ * row of Z by e[n-2] / |e[n-2]| afterwards (T = D T_r D^H with
+ * D = diag(1, ..., 1, e[n-2] / |e[n-2]|)).
+ * ------------------------------------------------------------------------ */
+
+/* Workspace bytes: about n * nev * 41 (the iterates, the LU factors and the
+ * pivot flags).  Errors: -1 n < 0, -2 nev outside [0, n], -3 null `bytes`. */
+int trbt_tridiag_eigh_workspace_bytes(int64_t n, int64_t nev, size_t *bytes);
+
+/* Arguments: 1 n >= 0, 2 0 <= nev <= n, 3 d (device, n), 4 e (device, n-1),
+ * 5 w (device, nev, out: eigenvalues ascending), 6 Z (device, n x nev
+ * column-major, out), 7 ldz >= max(1, n), 8 work (device, aligned to
+ * TRBT_WORK_ALIGN), 9 work_bytes (at least trbt_tridiag_eigh_workspace_bytes),
+ * 10 stream.  nev == 0 returns at once.  Asynchronous on `stream`; no
+ * allocation; TRBT_ERR_WORKSPACE when work is missing or too small. */
+int trbt_tridiag_eigh_d(int64_t n, int64_t nev, const double *d, const double *e, double *w,
+                        double *Z, int64_t ldz, void *work, size_t work_bytes, void *stream);
+
 /* Static description of a status code (never NULL). */
 const char *trbt_strerror(int status);
 

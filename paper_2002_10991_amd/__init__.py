@@ -27,7 +27,8 @@ __all__ = [
     "trans_ev_tridi_to_band_bwd_ckpt_d", "adjoint", "BackTransform", "back_transform_autograd",
     "trbt_band_to_tridi_workspace_bytes", "trbt_band_to_tridi_d", "trbt_band_to_tridi_z",
     "trbt_adjoint_workspace_bytes_z", "trans_ev_tridi_to_band_adjoint_z",
-    "band_to_tridiagonal",
+    "band_to_tridiagonal", "trbt_tridiag_eigh_workspace_bytes", "trbt_tridiag_eigh_d",
+    "tridiagonal_eigh",
 ]
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
@@ -95,6 +96,10 @@ def lib():
         L.trans_ev_tridi_to_band_adjoint_z.argtypes = \
             L.trans_ev_tridi_to_band_adjoint_d.argtypes
         L.trans_ev_tridi_to_band_adjoint_z.restype = i32
+        L.trbt_tridiag_eigh_workspace_bytes.argtypes = [i64, i64, C.POINTER(sz)]
+        L.trbt_tridiag_eigh_workspace_bytes.restype = i32
+        L.trbt_tridiag_eigh_d.argtypes = [i64, i64, vp, vp, vp, vp, i64, vp, sz, vp]
+        L.trbt_tridiag_eigh_d.restype = i32
         L.trbt_band_to_tridi_workspace_bytes.argtypes = [i64, i32, i32, C.POINTER(sz)]
         L.trbt_band_to_tridi_workspace_bytes.restype = i32
         for f in (L.trbt_band_to_tridi_d, L.trbt_band_to_tridi_z):
@@ -591,3 +596,41 @@ def band_to_tridiagonal(ab, nbw: int, work=None, stream=None):
     if rc:
         raise TrbtError(rc, f.__name__)
     return d, e, hv, ht
+
+
+# --------------------------------------------------------------------------
+# Tridiagonal eigenpairs (bisection + inverse iteration)
+# --------------------------------------------------------------------------
+def trbt_tridiag_eigh_workspace_bytes(n: int, nev: int) -> int:
+    nb = C.c_size_t()
+    rc = lib().trbt_tridiag_eigh_workspace_bytes(n, nev, C.byref(nb))
+    if rc:
+        raise TrbtError(rc, "trbt_tridiag_eigh_workspace_bytes")
+    return nb.value
+
+
+def trbt_tridiag_eigh_d(n, nev, d, e, w, Z, ldz, work, work_bytes, stream=None) -> int:
+    return lib().trbt_tridiag_eigh_d(n, nev, _ptr(d), _ptr(e), _ptr(w), _ptr(Z), ldz,
+                                     _ptr(work), work_bytes, _stream(stream))
+
+
+def tridiagonal_eigh(d, e, nev: int, stream=None):
+    """The lowest nev eigenpairs of the real symmetric tridiagonal
+    diag(d) + subdiag(e) on the GPU.  d (n,), e (n-1,) float64 device
+    tensors.  Returns (w (nev,), Z (n, nev) column-major view)."""
+    import torch
+    n = d.shape[0]
+    if d.dtype != torch.float64 or e.dtype != torch.float64:
+        raise TypeError("d and e must be float64")
+    w = torch.empty(nev, dtype=torch.float64, device=d.device)
+    zb = torch.empty((max(nev, 1), max(n, 1)), dtype=torch.float64, device=d.device)
+    nb = trbt_tridiag_eigh_workspace_bytes(n, nev)
+    work = None
+    if nb:
+        buf = torch.empty(nb + TRBT_WORK_ALIGN, dtype=torch.uint8, device=d.device)
+        work = buf[(-buf.data_ptr()) % TRBT_WORK_ALIGN:][:nb]
+    rc = trbt_tridiag_eigh_d(n, nev, d.contiguous(), e.contiguous(), w, zb, max(n, 1), work,
+                             nb, stream)
+    if rc:
+        raise TrbtError(rc, "trbt_tridiag_eigh_d")
+    return w, zb[:nev].T[:n]

@@ -299,3 +299,33 @@ def test_band_to_tridi_workspace_formula(T, n, nbw):
     assert T.trbt_band_to_tridi_workspace_bytes(0, 4, False) == 0
     with pytest.raises(T.TrbtError):
         T.trbt_band_to_tridi_workspace_bytes(10, 65, False)
+
+
+def test_tridiag_eigh_validation_codes(T):
+    f = T.trbt_tridiag_eigh_d
+    ok = dict(n=100, nev=10, d=FAKE, e=FAKE, w=FAKE, Z=FAKE, ldz=100, work=None, wb=0)
+
+    def call(**kw):
+        a = dict(ok, **kw)
+        return f(a["n"], a["nev"], a["d"], a["e"], a["w"], a["Z"], a["ldz"], a["work"], a["wb"], 0)
+
+    assert call(n=-1) == -1
+    assert call(nev=-1) == -2
+    assert call(nev=101) == -2
+    assert call(d=None) == -3
+    assert call(e=None) == -4
+    assert call(w=None) == -5
+    assert call(Z=None) == -6
+    assert call(ldz=99) == -7
+    assert call(work=FAKE + 8, wb=1 << 20) == -8
+    assert call() == -101                       # TRBT_ERR_WORKSPACE
+    assert call(nev=0, d=None, e=None, w=None, Z=None) == 0
+    assert call(n=1, nev=1, ldz=1, e=None) == -101   # n = 1 needs no e; only the workspace missing
+
+
+@pytest.mark.parametrize("n,nev", [(1, 1), (100, 10), (8192, 4096)])
+def test_tridiag_eigh_workspace_formula(T, n, nev):
+    al = lambda x: (x + 255) // 256 * 256
+    want = al(max(n - 1, 1) * 8) + al(32) + al(n * nev * 8) + al(n * nev * 32) + al(n * nev)
+    assert T.trbt_tridiag_eigh_workspace_bytes(n, nev) == want
+    assert T.trbt_tridiag_eigh_workspace_bytes(n, 0) == 0

@@ -1,0 +1,176 @@
+"""GPU tridiagonal eigenpairs (bisection + inverse iteration, the step of
+Eq. 2stage_solve) through the C ABI, against the oracle's implicit QL (pinned
+by the Toeplitz closed form, Jacobi and LAPACK), closed forms and
+invariants, and the whole stage 2 on the GPU (chase, tridiagonal solve,
+back-transformation).
+
+Bounds (FP64, eps = 2.2e-16, ||T|| the largest row sum):
+  * eigenvalues: |w - w_QL| <= 1e-13 ||T|| (bisection stops at a few ulps of
+    the eigenvalue; QL is accurate to O(eps ||T||));
+  * eigenvectors: residual ||T z - w z|| <= 1e-13 ||T||, and the angle to the
+    QL vector <= 1e-9 (inverse iteration's error is eps ||T|| / gap, gaps of
+    these random matrices are >= 1e-5 ||T||);
+  * orthogonality ||Z^T Z - I||_F <= 1e-12 n (the end-to-end bound).
+"""
+import numpy as np
+import pytest
+
+from conftest import gpu_available
+
+pytestmark = [pytest.mark.gpu,
+              pytest.mark.skipif(not gpu_available(), reason="needs a GPU")]
+
+
+def _gpu(d, e, nev, label=""):
+    import torch
+    import paper_2002_10991_amd as T
+    n = len(d)
+    print(f"[gpu] tridiag_eigh {label} n={n} nev={nev}", flush=True)
+    dd = torch.from_numpy(np.ascontiguousarray(d, dtype=np.float64)).to("cuda")
+    ee = torch.from_numpy(np.ascontiguousarray(e if n > 1 else np.zeros(1),
+                                               dtype=np.float64)).to("cuda")
+    w, Z = T.tridiagonal_eigh(dd, ee, nev)
+    torch.cuda.synchronize()
+    return w.cpu().numpy(), Z.cpu().numpy()
+
+
+def _tnorm(d, e):
+    ae = np.abs(e)
+    r = np.abs(d).copy()
+    r[:-1] += ae
+    r[1:] += ae
+    return float(r.max())
+
+
+def _tmul(d, e, Z):
+    Y = d[:, None] * Z
+    Y[:-1] += e[:, None] * Z[1:]
+    Y[1:] += e[:, None] * Z[:-1]
+    return Y
+
+
+def _check(d, e, w, Z, wref=None, Zref=None):
+    n, nev = Z.shape
+    tn = _tnorm(d, e)
+    if wref is not None:
+        assert np.max(np.abs(w - wref[:nev])) <= 1e-13 * tn
+    assert np.all(np.diff(w) >= 0)
+    R = _tmul(d, e, Z) - Z * w
+    assert np.max(np.linalg.norm(R, axis=0)) <= 1e-13 * tn * max(1.0, np.sqrt(n) / 10)
+    assert np.linalg.norm(Z.T @ Z - np.eye(nev)) <= 1e-12 * n
+    if Zref is not None:
+        cos = np.abs(np.sum(Z * Zref[:, :nev], axis=0))
+        assert np.all(1 - cos <= 1e-9)
+
+
+@pytest.mark.parametrize("n,nev", [(1, 1), (2, 2), (3, 1), (50, 50), (300, 150), (1000, 333),
+                                   (513, 17)])
+def test_tridiag_vs_oracle_ql(oracle_mod, n, nev):
+    rng = np.random.default_rng(100 + n)
+    d = rng.standard_normal(n)
+    e = rng.standard_normal(max(n - 1, 0))
+    wq, Xq = oracle_mod.tridiagonal_eigh(d, e)
+    w, Z = _gpu(d, e, nev, "random")
+    _check(d, e, w, Z, wq, Xq)
+
+
+def test_tridiag_of_a_chased_band(oracle_mod):
+    import synth
+    n, nbw, nev = 600, 16, 300
+    ab = synth.band_matrix(n, nbw, 61, "d", diag_shift=True)
+    r = oracle_mod.band_to_tridiagonal(ab, nbw)
+    wq, Xq = oracle_mod.tridiagonal_eigh(r["d"], r["e"])
+    w, Z = _gpu(r["d"], r["e"], nev, "chased band")
+    _check(r["d"], r["e"], w, Z, wq, Xq)
+
+
+def test_tridiag_toeplitz_closed_form():
+    n, a, b = 200, 2.0, -1.0
+    d, e = np.full(n, a), np.full(n - 1, b)
+    w, Z = _gpu(d, e, n, "toeplitz")
+    k = np.arange(1, n + 1)
+    lam = np.sort(a + 2 * b * np.cos(k * np.pi / (n + 1)))
+    assert np.max(np.abs(w - lam)) <= 1e-13 * 4
+    # eigenvector of lambda_k ~ sin(j k pi / (n+1)); lambda ascending <-> k ascending for b < 0
+    j = np.arange(1, n + 1)
+    for col in (0, 1, 57, n - 1):
+        kk = col + 1
+        v = np.sin(j * kk * np.pi / (n + 1))
+        v /= np.linalg.norm(v)
+        assert 1 - abs(v @ Z[:, col]) <= 1e-10
+
+
+def test_tridiag_diagonal_and_degenerate_shapes():
+    import torch
+    import paper_2002_10991_amd as T
+    d = np.array([3.0, -1.0, 2.0, 0.5, -4.0])
+    w, Z = _gpu(d, np.zeros(4), 5, "diagonal")
+    order = np.argsort(d)
+    assert np.max(np.abs(w - d[order])) <= 8 * 2.2e-16 * 4.0   # bisection: a few ulps
+    assert np.allclose(np.abs(Z), np.eye(5)[:, order], atol=1e-15)
+    # nev = 0 and n = 0: nothing to do
+    z = torch.zeros(0, dtype=torch.float64, device="cuda")
+    w0, Z0 = T.tridiagonal_eigh(torch.ones(3, dtype=torch.float64, device="cuda"),
+                                torch.ones(2, dtype=torch.float64, device="cuda"), 0)
+    assert w0.numel() == 0 and Z0.shape == (3, 0)
+    w0, Z0 = T.tridiagonal_eigh(z, z, 0)
+    assert w0.numel() == 0
+
+
+def test_tridiag_c2_shape_against_lapack():
+    """n = 8192, lowest 4096 (the real workload's tridiagonal size): the
+    tridiagonal comes from the GPU chase of that workload's band."""
+    import scipy.linalg as sl
+    import synth
+    import torch
+    import paper_2002_10991_amd as T
+    n, nbw, nev = 8192, 64, 4096
+    ab = synth.band_matrix(n, nbw, 1002, "d", diag_shift=True)
+    d, e, _, _ = T.band_to_tridiagonal(torch.from_numpy(np.ascontiguousarray(ab.T)).to("cuda"),
+                                       nbw)
+    torch.cuda.synchronize()
+    d, e = d.cpu().numpy(), e.cpu().numpy()
+    w, Z = _gpu(d, e, nev, "C2 shape")
+    wl = sl.eigvalsh_tridiagonal(d, e, select="i", select_range=(0, nev - 1))
+    tn = _tnorm(d, e)
+    assert np.max(np.abs(w - wl)) <= 1e-13 * tn
+    R = _tmul(d, e, Z) - Z * w
+    assert np.max(np.linalg.norm(R, axis=0)) <= 1e-13 * tn * np.sqrt(n) / 10
+    cols = np.random.default_rng(3).choice(nev, 512, replace=False)
+    S = Z[:, cols]
+    assert np.linalg.norm(S.T @ S - np.eye(len(cols))) <= 1e-12 * n
+
+
+@pytest.mark.parametrize("dtype", ["d", "z"])
+def test_stage2_entirely_on_gpu(dtype):
+    """Chase, tridiagonal eigenpairs and back-transformation all on the GPU:
+    the result are eigenvectors of the band matrix B."""
+    import torch
+    import synth
+    import paper_2002_10991_amd as T
+    n, nbw, nev = 1024, 32, 256
+    ab = synth.band_matrix(n, nbw, 808, dtype)
+    d, e, hv, ht = T.band_to_tridiagonal(torch.from_numpy(np.ascontiguousarray(ab.T)).to("cuda"),
+                                         nbw)
+    if dtype == "z":   # every subdiagonal but the last is a real beta: keep its sign
+        ea = e.real.clone()
+        ea[-1] = e[-1].abs()
+    else:
+        ea = e
+    w, Zr = T.tridiagonal_eigh(d, ea.to(torch.float64).contiguous(), nev)
+    if dtype == "z":
+        Zc = Zr.to(torch.complex128)
+        Zc[-1, :] *= (e[-1] / e[-1].abs())   # T = D T_r D^H, D = diag(1, .., 1, phase)
+    else:
+        Zc = Zr
+    buf = torch.empty((nev, n), dtype=Zc.dtype, device="cuda")
+    buf.copy_(Zc.T)
+    print(f"[gpu] back_transform stage-2 n={n} nbw={nbw} nev={nev} {dtype}", flush=True)
+    T.back_transform(buf.T, hv, ht, nbw)
+    torch.cuda.synchronize()
+    Y = buf.cpu().numpy().T
+    w = w.cpu().numpy()
+    B = synth.dense_from_band(ab)
+    res = np.linalg.norm(B @ Y - Y * w) / (np.linalg.norm(B) * np.sqrt(nev))
+    orth = np.linalg.norm(Y.conj().T @ Y - np.eye(nev))
+    assert res <= 1e-13 and orth <= 1e-12 * n
