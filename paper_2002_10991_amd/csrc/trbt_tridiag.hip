@@ -6,11 +6,11 @@
 //
 // Method (the classical pair, one thread per wanted eigenpair; the paper's
 // solver is divide and conquer, which reaches the same eigenpairs):
-//   * eigenvalue i by bisection on the Sturm count: the number of negative
-//     pivots of the LDL^T factorisation of T - x I equals the number of
-//     eigenvalues below x (Sylvester's law of inertia); the interval starts
-//     from the Gershgorin bounds and is halved until it is no wider than
-//     a few ulps of its end points;
+//   * eigenvalue i by multisection on the Sturm count: the number of
+//     negative pivots of the LDL^T factorisation of T - x I equals the number
+//     of eigenvalues below x (Sylvester's law of inertia); the interval
+//     starts from the Gershgorin bounds and is cut into 9 by 8 lanes per
+//     eigenvalue until it is no wider than a few ulps of its end points;
 //   * eigenvector i by inverse iteration with that eigenvalue: three solves
 //     (T - lambda I) x_{k+1} = x_k / ||x_k|| by Gaussian elimination with
 //     partial pivoting (the tridiagonal LU: U with two superdiagonals), from
@@ -92,27 +92,48 @@ __global__ __launch_bounds__(256) void k_td_prep(int64_t n, const double* __rest
     }
 }
 
-// eigenvalue i (0-based, ascending) by bisection
+// eigenvalue i (0-based, ascending) by multisection: TD_MS consecutive lanes
+// share one eigenvalue and evaluate the Sturm count at TD_MS interior points
+// of its interval, x_k = lo + (hi - lo)(k+1)/(TD_MS+1); the new interval is
+// [x_{k*-1}, x_{k*}] for the first point k* with count > i, read from the
+// group's bits of a wave ballot (every lane of the group computes the same
+// end points from the same formula).
+constexpr int TD_MS = 8;
+
 __global__ __launch_bounds__(TD_THREADS) void k_td_bisect(int64_t n, int64_t nev,
                                                           const double* __restrict__ d,
                                                           const double* __restrict__ e2,
                                                           const double* __restrict__ bounds,
                                                           double* __restrict__ w)
 {
-    const int64_t i = (int64_t)blockIdx.x * TD_THREADS + threadIdx.x;
-    if (i >= nev) return;
+    const int64_t gid = (int64_t)blockIdx.x * TD_THREADS + threadIdx.x;
+    const int64_t i = gid / TD_MS;
+    const int k = (int)(gid % TD_MS);
+    const int gbit = (threadIdx.x & 63) & ~(TD_MS - 1);   // the group's first lane in the wave
+    if (i >= nev) return;   // whole groups leave together
     double lo = bounds[0], hi = bounds[1];
     const double pivmin = bounds[3];
     const double eps = 2.220446049250313e-16;
     // invariant: count(lo) <= i < count(hi)
-    for (int it = 0; it < 200; ++it) {
-        const double mid = 0.5 * (lo + hi);
-        if (hi - lo <= 4.0 * eps * fmax(fabs(lo), fabs(hi)) + pivmin || mid <= lo || mid >= hi)
-            break;
-        if (sturm_count(n, d, e2, mid, pivmin) > i) hi = mid;
-        else lo = mid;
+    for (int it = 0; it < 100; ++it) {
+        if (hi - lo <= 4.0 * eps * fmax(fabs(lo), fabs(hi)) + pivmin) break;
+        const double step = (hi - lo) / (TD_MS + 1);
+        const double x = lo + step * (k + 1);
+        const bool above = sturm_count(n, d, e2, x, pivmin) > i;
+        const unsigned grp = (unsigned)((__ballot(above) >> gbit) & ((1u << TD_MS) - 1));
+        double nlo = lo, nhi = hi;
+        if (grp) {
+            const int ks = __builtin_ctz(grp);
+            nhi = lo + step * (ks + 1);
+            if (ks > 0) nlo = lo + step * ks;
+        } else {
+            nlo = lo + step * TD_MS;
+        }
+        if (nlo == lo && nhi == hi) break;   // no representable progress
+        lo = nlo;
+        hi = nhi;
     }
-    w[i] = 0.5 * (lo + hi);
+    if (k == 0) w[i] = 0.5 * (lo + hi);
 }
 
 // a fixed pseudo-random start in [-1, 1) (splitmix64 of (vector, row))
@@ -364,8 +385,9 @@ int trbt_tridiag_eigh_d(int64_t n, int64_t nev, const double* d, const double* e
     double* F = (double*)(ws + L.f);
     unsigned char* P = (unsigned char*)(ws + L.p);
     const unsigned nb = (unsigned)((nev + TD_THREADS - 1) / TD_THREADS);
+    const unsigned nbm = (unsigned)((nev * TD_MS + TD_THREADS - 1) / TD_THREADS);
     hipLaunchKernelGGL(k_td_prep, dim3(1), dim3(256), 0, st, n, d, e, e2, bounds);
-    hipLaunchKernelGGL(k_td_bisect, dim3(nb), dim3(TD_THREADS), 0, st, n, nev, d,
+    hipLaunchKernelGGL(k_td_bisect, dim3(nbm), dim3(TD_THREADS), 0, st, n, nev, d,
                        (const double*)e2, (const double*)bounds, w);
     hipLaunchKernelGGL(k_td_invit, dim3(nb), dim3(TD_THREADS), 0, st, n, nev, d, e,
                        (const double*)bounds, (const double*)w, X, F, P);
