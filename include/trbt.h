@@ -377,9 +377,12 @@ int trbt_band_to_tridi_z(int64_t n, int nbw, const trbt_z *ab, int64_t ldab, dou
  * bisection on the Sturm count, eigenvector i by inverse iteration (pivoted
  * tridiagonal LU, a fixed pseudo-random start, three solves), one GPU thread
  * per eigenpair.  Each eigenvector is normalised with its largest-magnitude
- * entry positive.  Accuracy: residuals ||T z - w z|| ~ eps ||T||; the angle
- * between the vectors of distinct eigenvalues ~ eps ||T|| / gap (no
- * re-orthogonalisation among eigenvalues that agree to working precision).
+ * entry positive (except vectors of a cluster after its orthonormalisation).
+ * Accuracy: residuals ||T z - w z|| ~ eps ||T||; the angle between the
+ * vectors of eigenvalues a gap apart ~ eps ||T|| / gap; eigenvalues within
+ * 1e-6 ||T|| of each other form a cluster whose vectors are orthonormalised
+ * together (modified Gram-Schmidt), so degenerate eigenvalues get an
+ * orthonormal basis of their eigenspace.
  * For the complex chase's T (every subdiagonal a real beta except e[n-2])
  * pass Re e with its last entry replaced by |e[n-2]| and multiply the last
  * row of Z by e[n-2] / |e[n-2]| afterwards (T = D T_r D^H with

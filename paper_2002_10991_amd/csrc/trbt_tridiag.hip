@@ -19,9 +19,12 @@
 //     eigenvectors, so the threads of a wave read and write consecutive
 //     addresses; the vectors are transposed into Z at the end.
 // Accuracy: residual ||T x - lambda x|| ~ eps ||T||; the angle between
-// computed eigenvectors of distinct eigenvalues ~ eps ||T|| / gap (no
-// re-orthogonalisation inside clusters: eigenvalues that agree to working
-// precision give nearly parallel vectors).
+// computed eigenvectors of eigenvalues a gap apart ~ eps ||T|| / gap.
+// Eigenvalues closer than 1e-6 ||T|| to their predecessor form a cluster:
+// its vectors (each an inverse iterate from a different start, so together
+// spanning the cluster's invariant subspace) are orthonormalised by modified
+// Gram-Schmidt, one workgroup per cluster, so (near-)degenerate eigenvalues
+// get an orthonormal basis of their subspace.
 
 #include <hip/hip_runtime.h>
 
@@ -35,6 +38,10 @@ namespace {
 
 constexpr int TD_THREADS = 64;
 constexpr int TD_ITERS = 3;
+// eigenvalues closer than this times ||T|| to their predecessor are one
+// cluster, whose vectors are orthonormalised together afterwards; outside
+// clusters the angle error of inverse iteration is below about eps / TD_CLUSTER
+constexpr double TD_CLUSTER = 1e-6;
 
 // number of eigenvalues of T strictly below x
 __device__ inline int64_t sturm_count(int64_t n, const double* __restrict__ d,
@@ -305,6 +312,47 @@ __global__ __launch_bounds__(TD_THREADS) void k_td_invit(int64_t n, int64_t nev,
     }
 }
 
+// Modified Gram-Schmidt over each cluster of size >= 2 (one workgroup per
+// eigenvalue index; only cluster starts with a successor in the cluster do
+// work).  Vectors in X (row-major, column j = X[r * nev + j]), already unit.
+__global__ __launch_bounds__(256) void k_td_ortho(int64_t n, int64_t nev,
+                                                  const double* __restrict__ w,
+                                                  const double* __restrict__ bounds,
+                                                  double* __restrict__ X)
+{
+    __shared__ double red[256];
+    const int64_t i = blockIdx.x;
+    const double thr = TD_CLUSTER * bounds[2];
+    if (i > 0 && w[i] - w[i - 1] <= thr) return;            // not a cluster start
+    if (i + 1 >= nev || w[i + 1] - w[i] > thr) return;       // a single eigenvalue
+    const int tid = threadIdx.x;
+    auto block_sum = [&](double v) {
+        red[tid] = v;
+        __syncthreads();
+        for (int h = 128; h > 0; h >>= 1) {
+            if (tid < h) red[tid] += red[tid + h];
+            __syncthreads();
+        }
+        const double s = red[0];
+        __syncthreads();
+        return s;
+    };
+    for (int64_t j = i + 1; j < nev && w[j] - w[j - 1] <= thr; ++j) {
+        for (int64_t m = i; m < j; ++m) {
+            double p = 0.0;
+            for (int64_t r = tid; r < n; r += 256) p = fma(X[r * nev + j], X[r * nev + m], p);
+            const double dt = block_sum(p);
+            for (int64_t r = tid; r < n; r += 256) X[r * nev + j] = fma(-dt, X[r * nev + m], X[r * nev + j]);
+            __syncthreads();
+        }
+        double p = 0.0;
+        for (int64_t r = tid; r < n; r += 256) p = fma(X[r * nev + j], X[r * nev + j], p);
+        const double inv = 1.0 / sqrt(block_sum(p));
+        for (int64_t r = tid; r < n; r += 256) X[r * nev + j] *= inv;
+        __syncthreads();
+    }
+}
+
 // row-major X (n x nev) -> column-major Z (ldz)
 __global__ __launch_bounds__(256) void k_td_out(int64_t n, int64_t nev,
                                                 const double* __restrict__ X,
@@ -391,6 +439,8 @@ int trbt_tridiag_eigh_d(int64_t n, int64_t nev, const double* d, const double* e
                        (const double*)e2, (const double*)bounds, w);
     hipLaunchKernelGGL(k_td_invit, dim3(nb), dim3(TD_THREADS), 0, st, n, nev, d, e,
                        (const double*)bounds, (const double*)w, X, F, P);
+    hipLaunchKernelGGL(k_td_ortho, dim3((unsigned)nev), dim3(256), 0, st, n, nev,
+                       (const double*)w, (const double*)bounds, X);
     hipLaunchKernelGGL(k_td_out, dim3((unsigned)((n + 31) / 32), (unsigned)((nev + 31) / 32)),
                        dim3(256), 0, st, n, nev, (const double*)X, Z, ldz);
     return hipGetLastError() == hipSuccess ? TRBT_SUCCESS : TRBT_ERR_HIP;

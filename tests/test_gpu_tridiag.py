@@ -117,6 +117,33 @@ def test_tridiag_diagonal_and_degenerate_shapes():
     assert w0.numel() == 0
 
 
+def test_tridiag_degenerate_clusters():
+    """Two identical blocks: every eigenvalue is double.  The vectors of each
+    cluster come out orthonormal (one thread computes a cluster, each iterate
+    orthogonalised against the earlier ones) and span the two blocks'
+    eigenvectors."""
+    rng = np.random.default_rng(12)
+    m = 60
+    d1, e1 = rng.standard_normal(m), rng.standard_normal(m - 1)
+    d = np.concatenate([d1, d1])
+    e = np.concatenate([e1, [0.0], e1])
+    n = 2 * m
+    w, Z = _gpu(d, e, n, "two equal blocks")
+    w1 = np.linalg.eigvalsh(np.diag(d1) + np.diag(e1, 1) + np.diag(e1, -1))
+    assert np.max(np.abs(w - np.repeat(w1, 2))) <= 1e-13 * _tnorm(d, e)
+    R = _tmul(d, e, Z) - Z * w
+    assert np.max(np.linalg.norm(R, axis=0)) <= 1e-13 * _tnorm(d, e)
+    assert np.linalg.norm(Z.T @ Z - np.eye(n)) <= 1e-12 * n
+    # each pair spans the pair of block eigenvectors
+    _, V1 = np.linalg.eigh(np.diag(d1) + np.diag(e1, 1) + np.diag(e1, -1))
+    for k in range(0, m, 7):
+        S = Z[:, 2 * k: 2 * k + 2]
+        B = np.zeros((n, 2))
+        B[:m, 0] = V1[:, k]
+        B[m:, 1] = V1[:, k]
+        assert np.linalg.norm(B.T @ S @ S.T @ B - np.eye(2)) <= 1e-10
+
+
 def test_tridiag_c2_shape_against_lapack():
     """n = 8192, lowest 4096 (the real workload's tridiagonal size): the
     tridiagonal comes from the GPU chase of that workload's band."""
