@@ -375,7 +375,7 @@ int trbt_band_to_tridi_z(int64_t n, int nbw, const trbt_z *ab, int64_t ldab, dou
  * real symmetric tridiagonal T = diag(d) + subdiag(e), ascending, and their
  * eigenvectors, computed only for the wanted ones -- eigenvalue i by
  * bisection on the Sturm count, eigenvector i by inverse iteration (pivoted
- * tridiagonal LU, a fixed pseudo-random start, three solves), one GPU thread
+ * tridiagonal LU, a fixed pseudo-random start, two solves), one GPU thread
  * per eigenpair.  Each eigenvector is normalised with its largest-magnitude
  * entry positive (except vectors of a cluster after its orthonormalisation).
  * Accuracy: residuals ||T z - w z|| ~ eps ||T||; the angle between the

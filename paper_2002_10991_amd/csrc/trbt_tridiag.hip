@@ -11,7 +11,7 @@
 //     of eigenvalues below x (Sylvester's law of inertia); the interval
 //     starts from the Gershgorin bounds and is cut into 9 by 8 lanes per
 //     eigenvalue until it is no wider than a few ulps of its end points;
-//   * eigenvector i by inverse iteration with that eigenvalue: three solves
+//   * eigenvector i by inverse iteration with that eigenvalue: two solves
 //     (T - lambda I) x_{k+1} = x_k / ||x_k|| by Gaussian elimination with
 //     partial pivoting (the tridiagonal LU: U with two superdiagonals), from
 //     a fixed pseudo-random start; an exactly zero pivot is replaced by
@@ -37,7 +37,7 @@
 namespace {
 
 constexpr int TD_THREADS = 64;
-constexpr int TD_ITERS = 3;
+constexpr int TD_ITERS = 2;
 // eigenvalues closer than this times ||T|| to their predecessor are one
 // cluster, whose vectors are orthonormalised together afterwards; outside
 // clusters the angle error of inverse iteration is below about eps / TD_CLUSTER
