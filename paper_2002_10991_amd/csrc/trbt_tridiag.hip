@@ -9,7 +9,7 @@
 //   * eigenvalue i by multisection on the Sturm count: the number of
 //     negative pivots of the LDL^T factorisation of T - x I equals the number
 //     of eigenvalues below x (Sylvester's law of inertia); the interval
-//     starts from the Gershgorin bounds and is cut into 9 by 8 lanes per
+//     starts from the Gershgorin bounds and is cut into 17 by 16 lanes per
 //     eigenvalue until it is no wider than a few ulps of its end points;
 //   * eigenvector i by inverse iteration with that eigenvalue: two solves
 //     (T - lambda I) x_{k+1} = x_k / ||x_k|| by Gaussian elimination with
@@ -105,7 +105,7 @@ __global__ __launch_bounds__(256) void k_td_prep(int64_t n, const double* __rest
 // [x_{k*-1}, x_{k*}] for the first point k* with count > i, read from the
 // group's bits of a wave ballot (every lane of the group computes the same
 // end points from the same formula).
-constexpr int TD_MS = 8;
+constexpr int TD_MS = 16;
 
 __global__ __launch_bounds__(TD_THREADS) void k_td_bisect(int64_t n, int64_t nev,
                                                           const double* __restrict__ d,
