@@ -273,7 +273,7 @@ def adjoint_leg(warmup: int, plain: bool = True):
             fn()
         e1.record(stream)
         torch.cuda.synchronize()
-        if int(aw[:4].view(torch.int32).cpu()[0]):
+        if T.trbt_work_check(aw):
             raise RuntimeError("adjoint: device wait-timeout flag set")
         return e0.elapsed_time(e1) / reps
 
@@ -666,7 +666,7 @@ def main():
     torch.cuda.synchronize()
     t1 = time.perf_counter()
     if work is not None:
-        flag = int(work[:4].view(torch.int32).cpu()[0])
+        flag = T.trbt_work_check(work)
         if flag:
             raise RuntimeError("device wait-timeout flag set")
     prep_ms = float(np.mean([e[0].elapsed_time(e[1]) for e in evs]))

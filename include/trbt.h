@@ -32,10 +32,15 @@
  *
  * All data pointers are DEVICE pointers.  The caller owns every buffer.
  * Calls are asynchronous on the given HIP stream (pass the hipStream_t as
- * void*; NULL means the default stream), reentrant, and keep no state
- * between calls.  No entry point below allocates device memory or
- * synchronizes the device.  Kernel-time faults surface at the caller's next
- * synchronization, not as a return code.
+ * void*; NULL means the default stream) and reentrant.  The only state the
+ * library keeps between calls is a per-device cache of the architecture
+ * check (filled on a device's first call, never invalidated) and the plans
+ * a caller creates.  No entry point below allocates device memory or
+ * synchronizes the device, except plan creation and destruction and
+ * trbt_work_check.  Kernel-time faults surface at the caller's next
+ * synchronization, not as a return code; the bounded inter-workgroup waits
+ * of the blocked kernels report a timeout through the workspace's fault
+ * word (trbt_work_check).
  *
  * Return codes: TRBT_SUCCESS (0); -i when argument i (1-based) is invalid,
  * checked on the host before anything is launched; or one of the
@@ -88,8 +93,9 @@ int trbt_workspace_bytes(int64_t n, int nbw, int64_t nev, int is_complex, size_t
  * unless nev == 0 or n == 0), 7 ldz >= max(1, n), 8 work (device, aligned
  * to TRBT_WORK_ALIGN; may be NULL when 9 work_bytes is 0 and
  * trbt_workspace_bytes reports 0), 9 work_bytes, 10 stream.
- * The contents of `work` on entry do not matter; on exit they are
- * unspecified.  n < 3, nbw == 1 or nev == 0 return TRBT_SUCCESS without
+ * The contents of `work` on entry do not matter; on exit it holds the
+ * fault word (read it with trbt_work_check: nonzero means Z is invalid)
+ * and otherwise unspecified data.  n < 3, nbw == 1 or nev == 0 return TRBT_SUCCESS without
  * touching Z. */
 int trans_ev_tridi_to_band_d(int64_t n, int nbw, int64_t nev,
                              const double *hh_v, const double *hh_tau,
@@ -401,6 +407,25 @@ int trbt_tridiag_eigh_workspace_bytes(int64_t n, int64_t nev, size_t *bytes);
  * allocation; TRBT_ERR_WORKSPACE when work is missing or too small. */
 int trbt_tridiag_eigh_d(int64_t n, int64_t nev, const double *d, const double *e, double *w,
                         double *Z, int64_t ldz, void *work, size_t work_bytes, void *stream);
+
+/* Fault word of a workspace.  The blocked kernels of
+ * trans_ev_tridi_to_band_{d,z} / trbt_apply_{d,z}, of the real adjoints
+ * (trans_ev_tridi_to_band_adjoint_d, _fwd_ckpt_d, _bwd_ckpt_d) and of the
+ * complex adjoint keep 32 bits at offset 0 of their workspace: clear after
+ * trbt_prepare_*, at the start of a one-call transform or adjoint and at
+ * the start of fwd_ckpt (bwd_ckpt keeps it, so a pair reports both halves),
+ * set when a bounded wait between workgroups gave up (never expected; the
+ * outputs of that call -- Z, or G, dv, dtau -- are then INVALID although
+ * the call returned TRBT_SUCCESS).
+ * Arguments: 1 work (device, the workspace of such a call, aligned to
+ * TRBT_WORK_ALIGN; NULL when the call ran without one -- the streaming
+ * kernels have no waits -- which gives *fault = 0), 2 fault (host, out:
+ * 0 or 1), 3 stream (the stream the call ran on).
+ * Blocking: it synchronizes `stream` and then reads the word.  The word of
+ * the banded-to-tridiagonal workspace is not this one (that call reports a
+ * timeout by filling d with NaN).  Errors: -1 misaligned work, -2 null
+ * fault, TRBT_ERR_HIP. */
+int trbt_work_check(const void *work, int *fault, void *stream);
 
 /* Static description of a status code (never NULL). */
 const char *trbt_strerror(int status);

@@ -28,7 +28,7 @@ __all__ = [
     "trbt_band_to_tridi_workspace_bytes", "trbt_band_to_tridi_d", "trbt_band_to_tridi_z",
     "trbt_adjoint_workspace_bytes_z", "trans_ev_tridi_to_band_adjoint_z",
     "band_to_tridiagonal", "trbt_tridiag_eigh_workspace_bytes", "trbt_tridiag_eigh_d",
-    "tridiagonal_eigh",
+    "tridiagonal_eigh", "trbt_work_check",
 ]
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
@@ -122,6 +122,8 @@ def lib():
         L.trbt_plan_check.restype = i32
         L.trbt_plan_destroy.argtypes = [vp]
         L.trbt_plan_destroy.restype = i32
+        L.trbt_work_check.argtypes = [vp, C.POINTER(i32), vp]
+        L.trbt_work_check.restype = i32
         L.trbt_strerror.argtypes = [i32]
         L.trbt_strerror.restype = C.c_char_p
         _lib = L
@@ -147,6 +149,17 @@ def _stream(stream) -> int | None:
 
 def trbt_strerror(status: int) -> str:
     return lib().trbt_strerror(int(status)).decode()
+
+
+def trbt_work_check(work, stream=None) -> int:
+    """Synchronize `stream` and return the workspace's fault word (0 or 1):
+    nonzero means a bounded wait between workgroups gave up and the outputs
+    of the call that used `work` are invalid."""
+    f = C.c_int()
+    rc = lib().trbt_work_check(_ptr(work), C.byref(f), _stream(stream))
+    if rc:
+        raise TrbtError(rc, "trbt_work_check")
+    return f.value
 
 
 def trbt_num_reflectors(n: int, nbw: int) -> int:

@@ -82,6 +82,9 @@ int apply(int64_t n, int nbw, int64_t nev, const double* hv, const double* ht, d
         }
 #undef TRBT_MAIN
     } else {
+        // the streaming kernel has no waits: its fault word is always clear
+        if (work && work_bytes >= sizeof(unsigned))
+            hipLaunchKernelGGL(k_zero_words, dim3(1), dim3(64), 0, st, (unsigned*)work, 1);
         const unsigned grid = (unsigned)((nev + 63) / 64);
         if (CPLX)
             hipLaunchKernelGGL((k_unblocked<cd>), dim3(grid), dim3(64), 0, st, n, nbw, nev,
@@ -179,6 +182,21 @@ int trbt_apply_z(int64_t n, int nbw, int64_t nev, const trbt_z* hh_v, const trbt
 {
     return apply<true>(n, nbw, nev, (const double*)hh_v, (const double*)hh_tau, (double*)Z, ldz,
                        work, work_bytes, stream);
+}
+
+int trbt_work_check(const void* work, int* fault, void* stream)
+{
+    if (!fault) return -2;
+    *fault = 0;
+    if (work && ((uintptr_t)work % TRBT_WORK_ALIGN)) return -1;
+    hipStream_t st = (hipStream_t)stream;
+    if (hipStreamSynchronize(st) != hipSuccess) return TRBT_ERR_HIP;
+    if (!work) return TRBT_SUCCESS;
+    unsigned word = 0;
+    if (hipMemcpy(&word, work, sizeof word, hipMemcpyDeviceToHost) != hipSuccess)
+        return TRBT_ERR_HIP;
+    *fault = word != 0u;
+    return TRBT_SUCCESS;
 }
 
 const char* trbt_strerror(int status)

@@ -394,6 +394,8 @@ int trans_ev_tridi_to_band_adjoint_z(int64_t n, int nbw, int64_t nev, const trbt
     const ZLayout L = zlayout(n, nbw, nev);
     if (!work || work_bytes < L.total) return TRBT_ERR_WORKSPACE;
     char* ws = (char*)work;
+    // fault word: this form has no inter-workgroup waits, so it stays clear
+    hipLaunchKernelGGL(k_zero_words, dim3(1), dim3(64), 0, st, (unsigned*)work, 64);
     double* Zw = (double*)(ws + L.zw);
     double* Gw = (double*)(ws + L.gw);
     double* ck = (double*)(ws + L.ck);

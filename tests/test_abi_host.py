@@ -329,3 +329,12 @@ def test_tridiag_eigh_workspace_formula(T, n, nev):
     want = al(max(n - 1, 1) * 8) + al(32) + al(n * nev * 8) + al(n * nev * 32) + al(n * nev)
     assert T.trbt_tridiag_eigh_workspace_bytes(n, nev) == want
     assert T.trbt_tridiag_eigh_workspace_bytes(n, 0) == 0
+
+
+def test_work_check_validation(T):
+    """trbt_work_check rejects a null fault pointer and a misaligned
+    workspace before it touches the device."""
+    import ctypes as C
+    f = C.c_int(7)
+    assert T.lib().trbt_work_check(None, None, None) == -2
+    assert T.lib().trbt_work_check(FAKE + 8, C.byref(f), None) == -1

@@ -133,3 +133,35 @@ def test_complex_adjoint_full_n_column_subset(oracle_mod):
     rZ, rv, rt = oracle_mod.adjoint(Z, G, V, tau, nbw)
     gZ, gv, gt = gpu_adjoint_z(Z, G, V, tau, nbw)
     assert _relerr(gZ, rZ) <= TOL and _relerr(gv, rv) <= TOL and _relerr(gt, rt) <= TOL
+
+
+def test_complex_adjoint_c5_shape_512_columns(oracle_mod):
+    """n=4096, nbw=64 with 512 columns (32 strips of the column sums behind
+    grad v and grad tau): every output against the oracle."""
+    n, nbw, nev = 4096, 64, 512
+    Z, G, V, tau = _inputs(n, nbw, nev, 1005)
+    gZ, gv, gt = gpu_adjoint_z(Z, G, V, tau, nbw)
+    rZ, rv, rt = oracle_mod.adjoint(Z, G, V, tau, nbw)
+    e = (_relerr(gZ, rZ), _relerr(gv, rv), _relerr(gt, rt))
+    print(f"[gpu] complex adjoint nev=512 rel errors {e}", flush=True)
+    assert max(e) <= TOL
+
+
+@pytest.mark.parametrize("n,nbw,nev", [(300, 64, 40), (97, 7, 10)])
+def test_complex_adjoint_v0_not_one_nan_tail(oracle_mod, n, nbw, nev):
+    """Complex v[0] != 1 (v scaled by alpha, tau by 1/|alpha|^2) and NaN beyond
+    each reflector's length."""
+    import synth
+    Z, G, V, tau = _inputs(n, nbw, nev, 4200 + n)
+    lengths = synth.reflector_lengths(n, nbw)
+    rng = np.random.default_rng(n + 1)
+    alpha = rng.uniform(0.5, 2.0, len(tau)) * np.exp(1j * rng.uniform(0, 2 * np.pi, len(tau)))
+    V2 = V * alpha[:, None]
+    t2 = tau / np.abs(alpha) ** 2
+    Vn = V2.copy()
+    Vn[np.arange(nbw)[None, :] >= lengths[:, None]] = np.nan
+    rZ, rv, rt = oracle_mod.adjoint(Z, G, V2, t2, nbw)
+    gZ, gv, gt = gpu_adjoint_z(Z, G, Vn, t2, nbw)
+    mask = np.arange(nbw)[None, :] < lengths[:, None]
+    assert _relerr(gZ, rZ) <= TOL and _relerr(gt, rt) <= TOL
+    assert _relerr(gv[mask], rv[mask]) <= TOL and np.all(gv[~mask] == 0)

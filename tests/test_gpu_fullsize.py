@@ -2,9 +2,10 @@
 benchmark times (prepare + apply through the C ABI), on sampled columns the
 oracle computes one by one (columns are independent, Sec. 2.2.2).
 
-Full-size inputs are the seeded synthetic unitary reflectors (the CPU bulge
-chase at n = 8192 / 32768 takes minutes to hours); chase-produced reflectors
-are covered at n <= 2048 here and in test_gpu_parity.py."""
+Full-size inputs here are the seeded synthetic unitary reflectors (the CPU
+bulge chase at n = 32768 takes hours); the real n = 8192 workload on the
+inputs its definition names (reflectors of the chased band, lowest
+eigenvectors of T) is in test_gpu_workloads.py."""
 import numpy as np
 import pytest
 
@@ -34,7 +35,7 @@ def _run_prepare_apply(n, nbw, nev, V, tau, Z):
     assert appl(n, nbw, nev, Vd, td, Zbuf, n, work, wb) == 0
     torch.cuda.synchronize()
     if work is not None:
-        assert int(work[:4].view(torch.int32).cpu()[0]) == 0
+        assert T.trbt_work_check(work) == 0
     return Zbuf
 
 
@@ -42,7 +43,7 @@ def _sampled_check(oracle_mod, Zbuf, Z, V, tau, nbw, cols):
     out = Zbuf[cols].cpu().numpy().T
     ref = oracle_mod.back_transform(Z[:, cols], V, tau, nbw)
     err = np.linalg.norm(out - ref) / np.linalg.norm(ref)
-    print(f"[gpu] sampled columns {list(cols)}: rel err {err:.2e}", flush=True)
+    print(f"[gpu] {len(cols)} sampled columns: rel err {err:.2e}", flush=True)
     assert err <= TOL
     # the whole result stays an isometric image of the input
     nz = float(np.linalg.norm(Z))
@@ -50,6 +51,7 @@ def _sampled_check(oracle_mod, Zbuf, Z, V, tau, nbw, cols):
     assert abs(ny - nz) <= 1e-12 * nz
 
 
+@pytest.mark.timeout(900)
 @pytest.mark.parametrize("cfg", ["C2", "C3"])
 def test_full_size_sampled_columns(oracle_mod, cfg):
     import synth
@@ -60,9 +62,15 @@ def test_full_size_sampled_columns(oracle_mod, cfg):
     V, tau = synth.unitary_reflectors(lengths, nbw, c["seed"], dt)
     Z = synth.gaussian(n, nev, c["seed"] + 1, dt)
     Zbuf = _run_prepare_apply(n, nbw, nev, V, tau, Z)
-    # first, last, strip and slot-group boundaries, and a few inside
-    cols = np.unique(np.array([0, 1, 15, 16, 17, nev // 2, nev - 17, nev - 1,
-                               *np.random.default_rng(7).integers(0, nev, 8)]))
+    # first, last, strip and slot-group boundaries, and a seeded sample
+    # inside: 512 columns in all at the headline shape (the oracle takes
+    # about a minute for them on 16 host cores), 64 at the real one
+    edge = [0, 1, 15, 16, 17, 127, 128, nev // 2, nev - 17, nev - 16, nev - 1]
+    want = 512 if cfg == "C3" else 64
+    rest = np.setdiff1d(np.arange(nev), edge)
+    pick = np.random.default_rng(7).choice(rest, want - len(edge), replace=False)
+    cols = np.unique(np.concatenate([edge, pick]))
+    assert len(cols) == want
     _sampled_check(oracle_mod, Zbuf, Z, V, tau, nbw, cols)
 
 

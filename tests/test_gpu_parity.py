@@ -52,7 +52,7 @@ def gpu_back_transform(Z, V, tau, nbw, ldz=None, check_err=True):
     T.back_transform(Zd, Vd, td, nbw, work=work)
     torch.cuda.synchronize()
     if check_err and work is not None:
-        assert int(work[:4].view(torch.int32).cpu()[0]) == 0, "device wait timeout flag set"
+        assert T.trbt_work_check(work) == 0, "device wait timeout flag set"
     return buf.cpu().numpy(), work
 
 
@@ -160,3 +160,38 @@ def test_c1_pipeline_end_to_end(oracle_mod, dtype):
     nrm = np.linalg.norm(B)
     assert np.linalg.norm(B @ Y - Y * p["w"]) / nrm <= 1e-12 * n
     assert np.linalg.norm(np.conj(Y.T) @ Y - np.eye(n)) <= 1e-12 * n
+
+
+def _rescaled_nan_tail(V, tau, lengths, dtype, seed):
+    """The same reflectors H = I - tau v v^H written with v' = alpha v
+    (v'[0] = alpha != 1) and tau' = tau / |alpha|^2, and every stored entry
+    at a position >= len filled with NaN.  The header promises v[0] is read
+    and the tail is never read, so the product of reflectors is unchanged."""
+    rng = np.random.default_rng(seed)
+    K = len(tau)
+    mag = rng.uniform(0.5, 2.0, K) * rng.choice([-1.0, 1.0], K)
+    alpha = mag * np.exp(1j * rng.uniform(0, 2 * np.pi, K)) if dtype == "z" else mag
+    V2 = V * alpha[:, None]
+    t2 = tau / np.abs(alpha) ** 2
+    Vz = V2.copy()                       # zero tail: the oracle's own layout
+    tail = np.arange(V.shape[1])[None, :] >= np.asarray(lengths)[:, None]
+    V2[tail] = np.nan
+    return V2, t2, Vz
+
+
+@pytest.mark.parametrize("dtype", ["d", "z"])
+@pytest.mark.parametrize("n,nbw,nev", [(300, 64, 40), (200, 32, 33), (150, 16, 20),
+                                       (150, 24, 20), (97, 7, 10), (100, 128, 9)])
+def test_parity_v0_not_one_nan_tail(oracle_mod, dtype, n, nbw, nev):
+    """v[0] != 1 and NaN beyond each reflector's length, on the blocked
+    (nbw in {16, 32, 64}) and the streaming path (24, 7, 128)."""
+    Z, V, tau = _inputs(n, nbw, nev, dtype, 3000 + n + nbw, oracle_mod)
+    lengths = oracle_mod.reflector_table(n, nbw)[3]
+    V2, t2, Vz = _rescaled_nan_tail(V, tau, lengths, dtype, 5 + n)
+    assert np.all(np.abs(V2[:, 0]) != 1.0)
+    out, _ = gpu_back_transform(Z, V2, t2, nbw)
+    got = out[:, :n].T
+    assert np.all(np.isfinite(got))
+    assert _relerr(got, oracle_mod.back_transform(Z, Vz, t2, nbw)) <= TOL
+    # the same operator as the unscaled reflectors
+    assert _relerr(got, oracle_mod.back_transform(Z, V, tau, nbw)) <= TOL
