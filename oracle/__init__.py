@@ -64,6 +64,15 @@ def lib():
         L.orc_tridi_ql.argtypes = [_i64, _dp, _dp, _dp, _i64]
         L.orc_jacobi_d.argtypes = [_i64, _dp, _dp, _dp]
         L.orc_num_threads.restype = C.c_int
+        L.orc_full_reflectors.restype = _i64
+        L.orc_full_reflectors.argtypes = [_i64, _i64]
+        L.orc_full_to_band_d.argtypes = [_i64, _i64, _dp, _i64, _dp, _i64, _dp]
+        L.orc_full_to_band_z.argtypes = [_i64, _i64, C.c_void_p, _i64, C.c_void_p, _i64,
+                                         C.c_void_p]
+        L.orc_back_transform_full_d.argtypes = [_i64, _i64, _i64, _i64, _dp, _i64, _dp, _dp,
+                                                _i64]
+        L.orc_back_transform_full_z.argtypes = [_i64, _i64, _i64, _i64, C.c_void_p, _i64,
+                                                C.c_void_p, C.c_void_p, _i64]
         _lib = L
     return _lib
 
@@ -299,3 +308,61 @@ def stage2_pipeline(ab: np.ndarray, nbw: int, nev: int | None = None):
         Zin[-1, :] *= ph
     r.update(w=w[:nev], Z_in=np.asfortranarray(Zin))
     return r
+
+
+# --------------------------------------------------------------------------
+# Stage 1: full -> band reduction (Eq. 2stage_fwd1) and its back-transformation
+# (Eq. 2stage_bkwd2)
+# --------------------------------------------------------------------------
+def full_reflectors(n: int, nbw: int) -> int:
+    """Number of stage-1 reflectors: one per column j = 0 .. n-nbw-2."""
+    return int(lib().orc_full_reflectors(n, nbw))
+
+
+def full_to_band(A: np.ndarray, nbw: int):
+    """B = P A P^* for a dense Hermitian A (both triangles), one Householder
+    reflector per column.  Returns dict(B (n, n), hh_v (n, J) with reflector
+    j in rows [j+nbw, n) of column j, hh_tau (J,))."""
+    cplx = np.iscomplexobj(A)
+    dt = np.complex128 if cplx else np.float64
+    B = np.array(A, dtype=dt, order="F", copy=True)
+    n = B.shape[0]
+    J = full_reflectors(n, nbw)
+    V = np.zeros((max(n, 1), max(J, 1)), dt, order="F")
+    tau = np.zeros(max(J, 1), dt)
+    ld = max(n, 1)
+    if cplx:
+        rc = lib().orc_full_to_band_z(n, nbw, _v(B), ld, _v(V), ld, _v(tau))
+    else:
+        rc = lib().orc_full_to_band_d(n, nbw, _p(B), ld, _p(V), ld, _p(tau))
+    _check(rc, "full_to_band")
+    return dict(B=B, hh_v=V[:n, :J], hh_tau=tau[:J])
+
+
+def back_transform_full(Z: np.ndarray, hh_v: np.ndarray, hh_tau: np.ndarray, nbw: int,
+                        cols=None) -> np.ndarray:
+    """C = P^* Y: every stage-1 reflector, in reverse generation order, one
+    at a time, applied to the columns of Z (n, nev).  hh_v is (n, J) with
+    reflector j in rows [j+nbw, n) of column j.  Returns a Fortran copy;
+    ``cols`` restricts the work to those columns."""
+    Z = np.asarray(Z)
+    cplx = np.iscomplexobj(Z) or np.iscomplexobj(hh_v)
+    dt = np.complex128 if cplx else np.float64
+    if cols is not None:
+        Z = Z[:, np.asarray(cols)]
+    Y = np.array(Z, dtype=dt, order="F", copy=True)
+    n, nev = Y.shape
+    J = full_reflectors(n, nbw)
+    V = np.asfortranarray(hh_v, dtype=dt)
+    t = np.ascontiguousarray(hh_tau, dtype=dt)
+    if J == 0:
+        return Y
+    if V.shape != (n, J) or t.shape != (J,):
+        raise ValueError(f"hh_v must be ({n}, {J}) and hh_tau ({J},)")
+    ld = max(n, 1)
+    if cplx:
+        rc = lib().orc_back_transform_full_z(n, nbw, 0, nev, _v(V), ld, _v(t), _v(Y), ld)
+    else:
+        rc = lib().orc_back_transform_full_d(n, nbw, 0, nev, _p(V), ld, _p(t), _p(Y), ld)
+    _check(rc, "back_transform_full")
+    return Y

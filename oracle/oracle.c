@@ -810,3 +810,165 @@ int orc_jacobi_d(int64_t n, double *A, double *w, double *V)
     }
     return ORC_OK;
 }
+
+/* ------------------------------------------------------------------------
+ * Full -> band reduction (Sec. 2.1, Eq. 2stage_fwd1): B = P A P^*.
+ *
+ * The paper states what this step produces -- a Hermitian band matrix of
+ * semi-bandwidth b similar to A -- and that it is done with BLAS-3
+ * operations, not how.  The plain definition written here takes one
+ * Householder reflector per column (the column-at-a-time form of successive
+ * band reduction, Bischof, Lang and Sun): for j = 0, 1, ..., n-b-2 the
+ * reflector H_j = I - tau_j v_j v_j^H with H_j^H x = beta e1 (the standard
+ * method of Eq. householder) is built from x = A[j+b : n, j], and
+ * A <- H_j^H A H_j acts on rows and columns [j+b, n).  Column j is then
+ * beta e1 below row j+b-1 and stays so: later reflectors act on rows
+ * >= j+1+b only.  A blocked implementation groups consecutive reflectors
+ * into panels and yields the same reflectors up to rounding, because a
+ * column of a panel only ever sees the left updates of the panel's earlier
+ * reflectors (their right updates touch columns >= j+b).
+ *
+ * With J = max(0, n-b-1) reflectors, B = H_{J-1}^H ... H_0^H A H_0 ... H_{J-1},
+ * i.e. P = H_{J-1}^H ... H_0^H and P^* = H_0 H_1 ... H_{J-1}.
+ *
+ * A  n x n Hermitian, both triangles stored, column-major (lda >= n);
+ *    overwritten with B (entries outside the band are set to exact zeros
+ *    for the annihilated columns; nothing else is touched).
+ * V  n x J column-major (ldv >= n): column j holds v_j in rows [j+b, n)
+ *    with v_j[0] = 1 at row j+b; every other entry is set to zero.
+ * tau J entries.
+ * Lengths n-j-b of 1 (j = n-b-1) carry no reflector: there is nothing to
+ * annihilate (the complex case would only rotate the phase of one entry,
+ * which the band form does not require).
+ * ---------------------------------------------------------------------- */
+int64_t orc_full_reflectors(int64_t n, int64_t b)
+{
+    return (b >= 1 && n - b - 1 > 0) ? n - b - 1 : 0;
+}
+
+int orc_full_to_band_d(int64_t n, int64_t b, double *A, int64_t lda, double *V,
+                       int64_t ldv, double *tau)
+{
+    if (n < 0 || b < 1 || lda < (n > 1 ? n : 1) || ldv < (n > 1 ? n : 1)) return ORC_EARG;
+    const int64_t J = orc_full_reflectors(n, b);
+    for (int64_t j = 0; j < J; ++j) {
+        const int64_t r = j + b, m = n - r;
+        double *v = V + j * ldv;
+        for (int64_t i = 0; i < n; ++i) v[i] = 0.0;
+        double beta;
+        for (int64_t i = 0; i < m; ++i) v[r + i] = A[(r + i) + j * lda];
+        orc_larfg_d(m, v + r, &tau[j], &beta);
+        const double t = tau[j];
+        /* left: A[r:n, k] <- H^H A[r:n, k] for every column k != j */
+#pragma omp parallel for schedule(static)
+        for (int64_t k = 0; k < n; ++k) {
+            if (k == j) continue;
+            double *y = A + r + k * lda;
+            double d = 0.0;
+            for (int64_t i = 0; i < m; ++i) d += v[r + i] * y[i];
+            for (int64_t i = 0; i < m; ++i) y[i] -= t * d * v[r + i];
+        }
+        /* right: A[k, r:n] <- A[k, r:n] H for every row k != j */
+#pragma omp parallel for schedule(static)
+        for (int64_t k = 0; k < n; ++k) {
+            if (k == j) continue;
+            double d = 0.0;
+            for (int64_t i = 0; i < m; ++i) d += A[k + (r + i) * lda] * v[r + i];
+            for (int64_t i = 0; i < m; ++i) A[k + (r + i) * lda] -= t * d * v[r + i];
+        }
+        /* column j and row j: beta e1 */
+        for (int64_t i = 0; i < m; ++i) {
+            A[(r + i) + j * lda] = i == 0 ? beta : 0.0;
+            A[j + (r + i) * lda] = i == 0 ? beta : 0.0;
+        }
+    }
+    return ORC_OK;
+}
+
+int orc_full_to_band_z(int64_t n, int64_t b, zc *A, int64_t lda, zc *V, int64_t ldv, zc *tau)
+{
+    if (n < 0 || b < 1 || lda < (n > 1 ? n : 1) || ldv < (n > 1 ? n : 1)) return ORC_EARG;
+    const int64_t J = orc_full_reflectors(n, b);
+    for (int64_t j = 0; j < J; ++j) {
+        const int64_t r = j + b, m = n - r;
+        zc *v = V + j * ldv;
+        for (int64_t i = 0; i < n; ++i) v[i] = 0.0;
+        double beta;
+        for (int64_t i = 0; i < m; ++i) v[r + i] = A[(r + i) + j * lda];
+        orc_larfg_z(m, v + r, &tau[j], &beta);
+        const zc t = tau[j];
+        /* left: H^H y = y - conj(tau) v (v^H y) */
+#pragma omp parallel for schedule(static)
+        for (int64_t k = 0; k < n; ++k) {
+            if (k == j) continue;
+            zc *y = A + r + k * lda;
+            zc d = 0.0;
+            for (int64_t i = 0; i < m; ++i) d += conj(v[r + i]) * y[i];
+            for (int64_t i = 0; i < m; ++i) y[i] -= conj(t) * d * v[r + i];
+        }
+        /* right: y H = y - tau (y v) v^H for the rows y */
+#pragma omp parallel for schedule(static)
+        for (int64_t k = 0; k < n; ++k) {
+            if (k == j) continue;
+            zc d = 0.0;
+            for (int64_t i = 0; i < m; ++i) d += A[k + (r + i) * lda] * v[r + i];
+            for (int64_t i = 0; i < m; ++i) A[k + (r + i) * lda] -= t * d * conj(v[r + i]);
+        }
+        for (int64_t i = 0; i < m; ++i) {
+            A[(r + i) + j * lda] = i == 0 ? beta : 0.0;
+            A[j + (r + i) * lda] = i == 0 ? beta : 0.0;
+        }
+    }
+    return ORC_OK;
+}
+
+/* ------------------------------------------------------------------------
+ * Band -> full back-transformation (Sec. 2.1, Eq. 2stage_bkwd2):
+ * C = P^* Y = H_0 (H_1 ( ... (H_{J-1} Y))), i.e. the stage-1 reflectors
+ * applied one at a time in reverse generation order, each as
+ * y <- y - tau_j v_j (v_j^H y) on rows [j+b, n) (the operation of Eq.
+ * kernel).  v_j[0] is read from V (not assumed 1); entries of V outside
+ * rows [j+b, n) of column j are not read.  Columns c0 .. c1-1 of Z only;
+ * OpenMP over the independent columns.
+ * ---------------------------------------------------------------------- */
+int orc_back_transform_full_d(int64_t n, int64_t b, int64_t c0, int64_t c1, const double *V,
+                              int64_t ldv, const double *tau, double *Z, int64_t ldz)
+{
+    if (n < 0 || b < 1 || c0 < 0 || c1 < c0 || ldz < (n > 1 ? n : 1) || ldv < (n > 1 ? n : 1))
+        return ORC_EARG;
+    const int64_t J = orc_full_reflectors(n, b);
+#pragma omp parallel for schedule(dynamic, 1)
+    for (int64_t c = c0; c < c1; ++c) {
+        double *z = Z + c * ldz;
+        for (int64_t j = J - 1; j >= 0; --j) {
+            const int64_t r = j + b, m = n - r;
+            const double *v = V + j * ldv + r;
+            double d = 0.0;
+            for (int64_t i = 0; i < m; ++i) d += v[i] * z[r + i];
+            const double a = tau[j] * d;
+            for (int64_t i = 0; i < m; ++i) z[r + i] -= a * v[i];
+        }
+    }
+    return ORC_OK;
+}
+
+int orc_back_transform_full_z(int64_t n, int64_t b, int64_t c0, int64_t c1, const zc *V,
+                              int64_t ldv, const zc *tau, zc *Z, int64_t ldz)
+{
+    if (n < 0 || b < 1 || c0 < 0 || c1 < c0 || ldz < (n > 1 ? n : 1) || ldv < (n > 1 ? n : 1))
+        return ORC_EARG;
+    const int64_t J = orc_full_reflectors(n, b);
+#pragma omp parallel for schedule(dynamic, 1)
+    for (int64_t c = c0; c < c1; ++c) {
+        zc *z = Z + c * ldz;
+        for (int64_t j = J - 1; j >= 0; --j) {
+            const int64_t r = j + b, m = n - r;
+            const zc *v = V + j * ldv + r;
+            zc d = 0.0;
+            for (int64_t i = 0; i < m; ++i) d += conj(v[i]) * z[r + i];
+            const zc a = tau[j] * d;
+            for (int64_t i = 0; i < m; ++i) z[r + i] -= a * v[i];
+        }
+    }
+    return ORC_OK;
+}

@@ -199,3 +199,74 @@ def batched_sizes(count: int = 64, seed: int = 1004):
 def batched_seeds(count: int = 64, seed: int = 1004):
     """Per-problem band seeds for C4 from SeedSequence(seed).spawn(count)."""
     return [int(s.generate_state(1)[0]) for s in np.random.SeedSequence(seed).spawn(count)]
+
+
+def hermitian_matrix(n: int, seed: int, dtype: str = "d") -> np.ndarray:
+    """Dense Hermitian n x n matrix (Fortran order) with the entry law of the
+    band workloads: real N(0,1) (symmetric); complex off-diagonal N(0,1/2) +
+    i N(0,1/2), real diagonal N(0,1).  Draw order (default_rng(seed)): real
+    standard_normal((n, n)), lower triangle mirrored; complex diagonal
+    standard_normal(n), then real and imaginary parts standard_normal((n, n))
+    each, lower triangles used."""
+    rng = np.random.default_rng(seed)
+    if dtype == "z":
+        dg = rng.standard_normal(n)
+        re = rng.standard_normal((n, n))
+        im = rng.standard_normal((n, n))
+        L = np.tril(np.sqrt(0.5) * (re + 1j * im), -1)
+        A = L + L.conj().T + np.diag(dg).astype(np.complex128)
+    else:
+        L = np.tril(rng.standard_normal((n, n)))
+        A = L + np.tril(L, -1).T
+    return np.asfortranarray(A)
+
+
+def full_reflector_count(n: int, nbw: int) -> int:
+    """Input-format bookkeeping: the full-to-band reduction stores one
+    reflector per column j = 0 .. n-nbw-2 (rows [j+nbw, n) of column j of an
+    n x J array); a trailing length-1 piece carries none."""
+    return max(n - nbw - 1, 0) if nbw >= 1 else 0
+
+
+def full_unitary_reflectors(n: int, nbw: int, seed: int, dtype: str = "d", cols=None):
+    """Random unitary Householder reflectors with the shape of full-to-band
+    output: an (n, J) Fortran array whose column j holds v_j in rows
+    [j+nbw, n) (v_j[0] = 1, the rest N(0, 1/len), complex each part
+    N(0, 1/(2 len))) and zeros elsewhere, and tau as in unitary_reflectors
+    (real 2/||v||^2; complex (1 - e^{i theta})/||v||^2, theta ~ U(pi/2,
+    3pi/2)).  Column j depends only on (seed, j // 64), so ``cols`` returns
+    just those columns of V (and their tau)."""
+    J = full_reflector_count(n, nbw)
+    cols = np.arange(J) if cols is None else np.asarray(cols)
+    dt = _np_dtype(dtype)
+    V = np.zeros((n, len(cols)), dt, order="F")
+    tau = np.zeros(len(cols), dt)
+    CH = 64
+    nchunk = (J + CH - 1) // CH
+    seqs = np.random.SeedSequence(seed).spawn(max(nchunk, 1))
+    need = {}
+    for i, c in enumerate(cols):
+        need.setdefault(int(c) // CH, []).append((i, int(c)))
+
+    def fill(item):
+        ch, items = item
+        rng = np.random.default_rng(seqs[ch])
+        w = min(CH, J - ch * CH)
+        if dtype == "z":
+            blk = rng.standard_normal((w, n)) + 1j * rng.standard_normal((w, n))
+            blk *= np.sqrt(0.5)
+            theta = rng.uniform(0.5 * np.pi, 1.5 * np.pi, w)
+        else:
+            blk = rng.standard_normal((w, n))
+        for i, c in items:
+            q = c - ch * CH
+            r = c + nbw
+            m = n - r
+            v = blk[q, r:] / np.sqrt(m)
+            v[0] = 1.0
+            V[r:, i] = v
+            nrm2 = float(np.sum(np.abs(v) ** 2))
+            tau[i] = (1.0 - np.exp(1j * theta[q])) / nrm2 if dtype == "z" else 2.0 / nrm2
+
+    _parallel(fill, need.items())
+    return V, tau
