@@ -533,6 +533,80 @@ def tridiag_leg(steps: int, warmup: int, cpu: bool = True):
     return res
 
 
+def b2f_leg(steps: int, warmup: int, cpu: bool = True):
+    """The band-to-full back-transformation C = P^* Y (Eq. 2stage_bkwd2), the
+    step after the headline one, on the same problem shapes: complex
+    n = 32768, nbw = 64, nev = 8192 and real n = 8192, nbw = 64, nev = 4096,
+    with seeded synthetic stage-1 reflectors (one per column, rows
+    [j+nbw, n)) and a Gaussian Y; the oracle timed on a column sample."""
+    import torch
+    import synth
+    import paper_2002_10991_amd as T
+    dev = torch.device("cuda:0")
+    stream = torch.cuda.current_stream()
+    res = {}
+    for label, n, nev, dt, seed in (("complex n=32768", 32768, 8192, "z", 5006),
+                                    ("real n=8192", 8192, 4096, "d", 5005)):
+        nbw = 64
+        cplx = dt == "z"
+        t = time.perf_counter()
+        V, tau = synth.full_unitary_reflectors(n, nbw, seed, dt)
+        Y = synth.gaussian(n, nev, 5007, dt)
+        log(f"band_to_full {label}: inputs ready in {time.perf_counter() - t:.1f}s")
+        vb = torch.from_numpy(np.ascontiguousarray(V.T)).to(dev)
+        td = torch.from_numpy(tau).to(dev)
+        zb = torch.from_numpy(np.ascontiguousarray(Y.T)).to(dev)
+        nb = T.trbt_band_to_full_workspace_bytes(n, nbw, nev, cplx)
+        buf = torch.empty(nb + T.TRBT_WORK_ALIGN, dtype=torch.uint8, device=dev)
+        work = buf[(-buf.data_ptr()) % T.TRBT_WORK_ALIGN:][:nb]
+        f = T.trans_ev_band_to_full_z if cplx else T.trans_ev_band_to_full_d
+
+        def run():
+            rc = f(n, nbw, nev, vb, n, td, zb, n, work, nb, stream)
+            if rc:
+                raise T.TrbtError(rc, f.__name__)
+
+        for _ in range(max(warmup, 1)):
+            run()
+        torch.cuda.synchronize()
+        evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+               for _ in range(steps)]
+        for e0, e1 in evs:
+            e0.record(stream)
+            run()
+            e1.record(stream)
+        torch.cuda.synchronize()
+        ts = [a.elapsed_time(z) for a, z in evs]
+        ms = float(np.mean(ts))
+        m = n - nbw
+        L1 = m * (m + 1) // 2 - 1            # sum of the reflector lengths, 2 .. n-nbw
+        flops = (16 if cplx else 4) * nev * L1
+        r = {"n": n, "nbw": nbw, "nev": nev, "dtype": "c128" if cplx else "f64",
+             "reflectors": int(len(tau)), "ms": round(ms, 3), "ms_min": round(min(ts), 3),
+             "flops": flops, "achieved_tflops": round(flops / (ms / 1e3) / 1e12, 4),
+             "frac_fp64_peak": round(flops / (ms / 1e3) / 1e12 / PEAK_FP64_TFLOPS, 4),
+             "kernels": "k_b2f_tfac (compact-WY factors) + k_b2f_apply, per call",
+             "inputs": "synthetic unitary stage-1 reflectors + Gaussian Y, seeded"}
+        if cpu:
+            import oracle
+            ncols = 2 * oracle.num_threads()
+            cols = np.linspace(0, nev - 1, ncols).astype(np.int64)
+            t = time.perf_counter()
+            oracle.back_transform_full(Y, V, tau, nbw, cols=cols)
+            cs = time.perf_counter() - t
+            rate = (16 if cplx else 4) * L1 * ncols / cs
+            r["cpu_baseline"] = {"value": round(rate / 1e12, 6), "unit": "TFLOP/s",
+                                 "cores": oracle.num_threads(), "kind": "oracle",
+                                 "sample": f"{ncols} of {nev} columns, all reflectors, "
+                                           f"{cs:.1f} s wall"}
+            r["speedup_vs_oracle"] = round(flops / (ms / 1e3) / rate, 1)
+        log(f"band_to_full {label}: {ms:.2f} ms, {r['achieved_tflops']} TFLOP/s")
+        res[label] = r
+        del vb, zb, buf, work, V, Y
+        torch.cuda.empty_cache()
+    return res
+
+
 def committed_traffic(workload: str):
     """HBM bytes per launch of the apply kernel from the committed rocprofv3
     counter summary, if it was taken on the current kernel source; else None."""
@@ -576,6 +650,10 @@ def main():
                     help="skip the banded-to-tridiagonal bulge chasing leg")
     ap.add_argument("--chase-only", action="store_true",
                     help="run only the bulge chasing leg and print its JSON")
+    ap.add_argument("--no-b2f", action="store_true",
+                    help="skip the band-to-full back-transformation leg")
+    ap.add_argument("--b2f-only", action="store_true",
+                    help="run only the band-to-full back-transformation leg and print its JSON")
     ap.add_argument("--no-plain", action="store_true",
                     help="in the adjoint comparison, time only the hand-written adjoint")
     ap.add_argument("--copy-kernel", type=int, default=0, metavar="BYTES",
@@ -612,6 +690,10 @@ def main():
     if args.chase_only:
         print(json.dumps({"chase": chase_leg(args.steps, args.warmup,
                                              not args.no_cpu_baseline)}), flush=True)
+        return
+    if args.b2f_only:
+        print(json.dumps({"band_to_full": b2f_leg(args.steps, args.warmup,
+                                                  not args.no_cpu_baseline)}), flush=True)
         return
     if args.adjoint_only:
         print(json.dumps({"adjoint_vs_plain": adjoint_leg(args.warmup, not args.no_plain),
@@ -713,6 +795,8 @@ def main():
         out["adjoint_complex_vs_plain"] = adjoint_complex_leg(args.warmup, not args.no_plain)
     if not args.no_chase:
         out["chase"] = chase_leg(min(args.steps, 3), args.warmup, not args.no_cpu_baseline)
+    if not args.no_b2f:
+        out["band_to_full"] = b2f_leg(min(args.steps, 3), args.warmup, not args.no_cpu_baseline)
     if not args.no_tridiag:
         out["tridiag"] = tridiag_leg(min(args.steps, 3), args.warmup, not args.no_cpu_baseline)
     if not args.no_cpu_baseline:

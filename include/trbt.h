@@ -292,7 +292,14 @@ typedef struct trbt_plan trbt_plan;   /* opaque */
  * problems' Z (freed before returning) and keeps the fastest; the caller's
  * Z is not modified.  Candidates: strip_cols 16/32 x waves 4/8 with
  * block_stages 16, and block_stages 1 when no problem can take the blocked
- * form or every problem has n <= 256. */
+ * form or every problem has n <= 256.
+ * Tuning cache: when the environment variable TRBT_TUNE_CACHE names a file,
+ * a tuned plan's choice is appended to it as one text line keyed by the
+ * problem set's signature (device architecture and CU count, real or
+ * complex, the sorted (n, nbw, nev) of all problems -- not the pointers),
+ * and a later cfg == NULL plan with the same signature takes it from there
+ * without timing (trbt_plan_get_config then reports the cached time).  An
+ * unreadable or unwritable file only means tuning runs as without it. */
 int trbt_plan_create_batched_d(const trbt_problem_d *probs, int count,
                                const trbt_plan_config *cfg, trbt_plan **plan,
                                void *stream);
@@ -407,6 +414,54 @@ int trbt_tridiag_eigh_workspace_bytes(int64_t n, int64_t nev, size_t *bytes);
  * allocation; TRBT_ERR_WORKSPACE when work is missing or too small. */
 int trbt_tridiag_eigh_d(int64_t n, int64_t nev, const double *d, const double *e, double *w,
                         double *Z, int64_t ldz, void *work, size_t work_bytes, void *stream);
+
+/* ------------------------------------------------------------------------
+ * Band-to-full back-transformation (the step after the tridiagonal-to-
+ * banded one; Sec. 2.1, Eq. 2stage_bkwd2):
+ *
+ *     C = P^* Y,   P^* = H_0 H_1 ... H_{J-1},   H_j = I - tau_j v_j v_j^H,
+ *
+ * where B = P A P^* (Eq. 2stage_fwd1) is the full-to-band reduction of the
+ * Hermitian A with one reflector per column: v_j acts on rows [j+nbw, n)
+ * (j = 0 .. J-1, J = max(0, n-nbw-1)) and annihilates column j below the
+ * band.  The reflectors are applied in reverse generation order, each as
+ * y <- y - tau_j v_j (v_j^H y) on its rows (the operation of Eq. kernel);
+ * the library merges 64 consecutive reflectors into one compact-WY factor
+ * I - V T V^H and applies it with dense products on FP64 MFMA.
+ *
+ * Data layout:
+ *   hh_v    n x J, column-major, leading dimension ldv >= max(1, n):
+ *           column j holds v_j in rows [j+nbw, n), v_j[0] at row j+nbw
+ *           (read, not assumed to be 1).  Rows above j+nbw of column j and
+ *           rows n .. ldv-1 are never read (LAPACK keeps such reflectors
+ *           below the band of the reduced matrix; any storage with this
+ *           shape works).
+ *   hh_tau  J scalars.
+ *   Z       n x nev column-major (ldz >= max(1, n)), overwritten with C;
+ *           rows n .. ldz-1 are never read or written.
+ * ------------------------------------------------------------------------ */
+
+/* Workspace bytes: 256 + ceil(J/64) * 64 * 64 scalars (the per-panel
+ * compact-WY factors T); 0 when J == 0 or nev == 0.  Errors: -1 n < 0,
+ * -2 nbw < 1, -3 nev outside [0, n], -4 null `bytes`. */
+int trbt_band_to_full_workspace_bytes(int64_t n, int nbw, int64_t nev, int is_complex,
+                                      size_t *bytes);
+
+/* Arguments: 1 n >= 0, 2 nbw >= 1, 3 0 <= nev <= n, 4 hh_v (device, non-null
+ * unless J == 0 or nev == 0), 5 ldv >= max(1, n), 6 hh_tau (device, J),
+ * 7 Z (device, non-null unless nev == 0 or n == 0), 8 ldz >= max(1, n),
+ * 9 work (device, aligned to TRBT_WORK_ALIGN), 10 work_bytes (at least
+ * trbt_band_to_full_workspace_bytes), 11 stream.  J == 0 (n <= nbw+1) or
+ * nev == 0 return TRBT_SUCCESS without touching Z.  Asynchronous on
+ * `stream`, no allocation; TRBT_ERR_WORKSPACE when work is missing or too
+ * small.  The kernels have no waits between workgroups (the fault word
+ * stays clear).  Results are bitwise reproducible. */
+int trans_ev_band_to_full_d(int64_t n, int nbw, int64_t nev, const double *hh_v, int64_t ldv,
+                            const double *hh_tau, double *Z, int64_t ldz, void *work,
+                            size_t work_bytes, void *stream);
+int trans_ev_band_to_full_z(int64_t n, int nbw, int64_t nev, const trbt_z *hh_v, int64_t ldv,
+                            const trbt_z *hh_tau, trbt_z *Z, int64_t ldz, void *work,
+                            size_t work_bytes, void *stream);
 
 /* Fault word of a workspace.  The blocked kernels of
  * trans_ev_tridi_to_band_{d,z} / trbt_apply_{d,z}, of the real adjoints

@@ -41,8 +41,12 @@ def build(force: bool = False) -> str:
 def lib():
     global _lib
     if _lib is None:
-        build()
-        L = C.CDLL(_LIB)
+        # ORACLE_LIB: a prebuilt copy of oracle.c (the sanitizer test builds
+        # one with AddressSanitizer); default: build liboracle.so here
+        path = os.environ.get("ORACLE_LIB")
+        if not path:
+            path = build()
+        L = C.CDLL(path)
         L.orc_sweeps_in_stage.restype = _i64
         L.orc_sweeps_in_stage.argtypes = [_i64, _i64, _i64]
         L.orc_num_reflectors.restype = _i64

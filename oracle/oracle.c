@@ -649,8 +649,15 @@ int orc_adjoint_z(int64_t n, int64_t b, int64_t nev, const zc *hh_v, const zc *h
 
 /* ------------------------------------------------------------------------
  * Symmetric tridiagonal eigensolver, Eq. 2stage_solve, by the implicit QL
- * algorithm with Wilkinson shift (Golub & Van Loan, Sec. 8.3; the paper
- * itself uses divide and conquer, which reaches the same eigenpairs).
+ * algorithm with Wilkinson shift, in the published formulation of
+ * Bowdler, Martin, Reinsch and Wilkinson ("The QR and QL algorithms for
+ * symmetric matrices", Numer. Math. 11, 1968: the Handbook routine tql2, as
+ * restated in textbook form, e.g. Numerical Recipes' tqli): a small
+ * subdiagonal splits the matrix, the shift is the eigenvalue of the leading
+ * 2x2 block nearer d[l], and one sweep of plane rotations runs from the
+ * bottom of the unreduced block up (theory: Golub & Van Loan, Sec. 8.3).
+ * The paper itself uses divide and conquer, which reaches the same
+ * eigenpairs.
  * d (n) diagonal, e (n-1) subdiagonal (e[i] couples rows i and i+1).
  * On exit d holds the eigenvalues in ascending order and X (n x n,
  * column-major, ldx) the orthonormal eigenvectors in the same order.

@@ -28,11 +28,14 @@ __all__ = [
     "trbt_band_to_tridi_workspace_bytes", "trbt_band_to_tridi_d", "trbt_band_to_tridi_z",
     "trbt_adjoint_workspace_bytes_z", "trans_ev_tridi_to_band_adjoint_z",
     "band_to_tridiagonal", "trbt_tridiag_eigh_workspace_bytes", "trbt_tridiag_eigh_d",
-    "tridiagonal_eigh", "trbt_work_check",
+    "tridiagonal_eigh", "trbt_work_check", "trbt_band_to_full_workspace_bytes",
+    "trans_ev_band_to_full_d", "trans_ev_band_to_full_z", "band_to_full",
 ]
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(_HERE, "libtrbt.so")
+# TRBT_LIB selects another build of the same library (the host-sanitizer
+# and wait-jitter debug builds); default: the in-tree release build.
+LIB_PATH = os.environ.get("TRBT_LIB") or os.path.join(_HERE, "libtrbt.so")
 TRBT_WORK_ALIGN = 256
 TRBT_NBW_MAX = 256
 _lib = None
@@ -122,6 +125,11 @@ def lib():
         L.trbt_plan_check.restype = i32
         L.trbt_plan_destroy.argtypes = [vp]
         L.trbt_plan_destroy.restype = i32
+        L.trbt_band_to_full_workspace_bytes.argtypes = [i64, i32, i64, i32, C.POINTER(sz)]
+        L.trbt_band_to_full_workspace_bytes.restype = i32
+        for f in (L.trans_ev_band_to_full_d, L.trans_ev_band_to_full_z):
+            f.argtypes = [i64, i32, i64, vp, i64, vp, vp, i64, vp, sz, vp]
+            f.restype = i32
         L.trbt_work_check.argtypes = [vp, C.POINTER(i32), vp]
         L.trbt_work_check.restype = i32
         L.trbt_strerror.argtypes = [i32]
@@ -647,3 +655,62 @@ def tridiagonal_eigh(d, e, nev: int, stream=None):
     if rc:
         raise TrbtError(rc, "trbt_tridiag_eigh_d")
     return w, zb[:nev].T[:n]
+
+
+# --------------------------------------------------------------------------
+# Band -> full back-transformation (Eq. 2stage_bkwd2)
+# --------------------------------------------------------------------------
+def trbt_band_to_full_workspace_bytes(n: int, nbw: int, nev: int, is_complex: bool) -> int:
+    nb = C.c_size_t()
+    rc = lib().trbt_band_to_full_workspace_bytes(n, nbw, nev, int(bool(is_complex)),
+                                                 C.byref(nb))
+    if rc:
+        raise TrbtError(rc, "trbt_band_to_full_workspace_bytes")
+    return nb.value
+
+
+def trans_ev_band_to_full_d(n, nbw, nev, hh_v, ldv, hh_tau, Z, ldz, work, work_bytes,
+                            stream=None) -> int:
+    return lib().trans_ev_band_to_full_d(n, nbw, nev, _ptr(hh_v), ldv, _ptr(hh_tau), _ptr(Z), ldz,
+                                         _ptr(work), work_bytes, _stream(stream))
+
+
+def trans_ev_band_to_full_z(n, nbw, nev, hh_v, ldv, hh_tau, Z, ldz, work, work_bytes,
+                            stream=None) -> int:
+    return lib().trans_ev_band_to_full_z(n, nbw, nev, _ptr(hh_v), ldv, _ptr(hh_tau), _ptr(Z), ldz,
+                                         _ptr(work), work_bytes, _stream(stream))
+
+
+def band_to_full(Z, hh_v, hh_tau, nbw: int, work=None, stream=None):
+    """In-place C = P^* Y (Eq. 2stage_bkwd2) on a CUDA/HIP tensor.
+
+    Z: (n, nev) float64 or complex128 with unit row stride (column-major
+    view).  hh_v: (n, J) column-major view (unit row stride, e.g. ``buf.T``
+    of a (J, ldv) buffer), column j holding reflector j in rows
+    [j+nbw, n); hh_tau: (J,) contiguous.  Returns Z."""
+    import torch
+    n, nev = Z.shape
+    if nev and n and Z.stride(0) != 1:
+        raise ValueError("Z must be column-major (unit row stride)")
+    cplx = Z.dtype == torch.complex128
+    if not cplx and Z.dtype != torch.float64:
+        raise TypeError("Z must be float64 or complex128")
+    J = max(n - nbw - 1, 0)
+    if hh_v.dtype != Z.dtype or hh_tau.dtype != Z.dtype or not hh_tau.is_contiguous():
+        raise TypeError("hh_v and hh_tau must have Z's dtype (hh_tau contiguous)")
+    if J and (hh_v.shape[0] != n or hh_v.shape[1] < J or hh_v.stride(0) != 1):
+        raise ValueError(f"hh_v must be an ({n}, {J}) column-major view")
+    ldv = hh_v.stride(1) if J > 1 else max(n, 1)
+    ldz = Z.stride(1) if nev > 1 else max(n, 1)
+    if work is None:
+        nb = trbt_band_to_full_workspace_bytes(n, nbw, nev, cplx)
+        if nb:
+            buf = torch.empty(nb + TRBT_WORK_ALIGN, dtype=torch.uint8, device=Z.device)
+            work = buf[(-buf.data_ptr()) % TRBT_WORK_ALIGN:][:nb]
+    wb = 0 if work is None else work.numel() * work.element_size()
+    f = trans_ev_band_to_full_z if cplx else trans_ev_band_to_full_d
+    rc = f(n, nbw, nev, hh_v if J else None, max(ldv, n, 1), hh_tau if J else None, Z,
+           max(ldz, 1), work, wb, stream)
+    if rc:
+        raise TrbtError(rc, f.__name__)
+    return Z

@@ -22,16 +22,29 @@ HIPCC_FLAGS = [
 ]
 
 
-def build(verbose: bool = False) -> str:
+# Debug variant: every wait between waves is preceded by a pseudo-random
+# delay (TRBT_WAIT_JITTER in trbt_device.h), to run the hand-offs in many
+# orders.  Loaded instead of the release library with TRBT_LIB=<path>.
+OUT_JITTER = os.path.join(HERE, "libtrbt_jitter.so")
+
+
+def build(verbose: bool = False, out: str = OUT, extra=()) -> str:
     hipcc = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
-    tmp = OUT + f".tmp{os.getpid()}"
-    cmd = [hipcc, *HIPCC_FLAGS, "-I", os.path.join(ROOT, "include"), "-I", CSRC, *SRCS, "-o", tmp]
+    tmp = out + f".tmp{os.getpid()}"
+    cmd = [hipcc, *HIPCC_FLAGS, *extra, "-I", os.path.join(ROOT, "include"), "-I", CSRC, *SRCS,
+           "-o", tmp]
     if verbose:
         print(" ".join(cmd), flush=True)
     subprocess.check_call(cmd)
-    os.replace(tmp, OUT)
-    return OUT
+    os.replace(tmp, out)
+    return out
+
+
+def build_jitter(verbose: bool = False) -> str:
+    return build(verbose, OUT_JITTER, ("-DTRBT_WAIT_JITTER",))
 
 
 if __name__ == "__main__":
     print(build(verbose="-v" in sys.argv))
+    if "--jitter" in sys.argv:
+        print(build_jitter(verbose="-v" in sys.argv))

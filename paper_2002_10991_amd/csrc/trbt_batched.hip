@@ -31,15 +31,23 @@
 // candidate (strip width 16 or 32 columns (complex: 16), 4 or 8 waves per
 // workgroup, 16-stage compact-WY blocks; one reflector at a time as well
 // when no problem can take the blocked form or all have n <= 256) on scratch
-// copies of the problems' Z and keeps the fastest.
+// copies of the problems' Z and keeps the fastest.  With the environment
+// variable TRBT_TUNE_CACHE naming a file, the result is kept there, keyed by
+// a signature of the problem set (device architecture and CU count, real or
+// complex, and the sorted (n, nbw, nev) of every problem), and a later plan
+// of the same signature takes it without timing anything.
 
 #include <hip/hip_runtime.h>
 
 #include <stdint.h>
 #include <string.h>
 
+#include <stdio.h>
+#include <stdlib.h>
+
 #include <algorithm>
 #include <new>
+#include <tuple>
 #include <vector>
 
 #include "trbt.h"
@@ -452,7 +460,90 @@ void release(trbt_plan* P)
     delete P;
 }
 
+int tune_by_timing(trbt_plan& P);
+
+// --------------------------------------------------------------------------
+// Tuning cache (TRBT_TUNE_CACHE): one text line per tuned problem set,
+//   trbt-tune-v1 <signature> <strip_cols> <waves> <block_stages> <best ms>
+// appended after tuning; the last line of a signature wins.
+// --------------------------------------------------------------------------
+uint64_t plan_signature(const trbt_plan& P)
+{
+    hipDeviceProp_t prop;
+    const char* arch = "unknown";
+    if (hipGetDeviceProperties(&prop, P.device) == hipSuccess) arch = prop.gcnArchName;
+    std::vector<std::tuple<int64_t, int, int64_t>> shapes;
+    for (const trbt_problem_d& p : P.probs) shapes.emplace_back(p.n, p.nbw, p.nev);
+    std::sort(shapes.begin(), shapes.end());
+    uint64_t h = 1469598103934665603ull;   // FNV-1a, 64 bit
+    auto mix = [&h](const void* data, size_t len) {
+        const unsigned char* c = (const unsigned char*)data;
+        for (size_t i = 0; i < len; ++i) h = (h ^ c[i]) * 1099511628211ull;
+    };
+    mix(arch, strlen(arch));
+    mix(&P.cus, sizeof P.cus);
+    const int cp = P.cplx ? 1 : 0;
+    mix(&cp, sizeof cp);
+    for (const auto& t : shapes) {
+        const int64_t a = std::get<0>(t), c = std::get<2>(t);
+        const int b = std::get<1>(t);
+        mix(&a, sizeof a);
+        mix(&b, sizeof b);
+        mix(&c, sizeof c);
+    }
+    return h;
+}
+
+bool cache_lookup(const char* path, uint64_t sig, bool cplx, trbt_plan_config* cfg, double* ms)
+{
+    FILE* f = fopen(path, "r");
+    if (!f) return false;
+    bool found = false;
+    char line[256];
+    while (fgets(line, sizeof line, f)) {
+        unsigned long long s = 0;
+        trbt_plan_config c{};
+        double t = 0.0;
+        if (sscanf(line, "trbt-tune-v1 %llx %d %d %d %lf", &s, &c.strip_cols, &c.waves,
+                   &c.block_stages, &t) == 5 &&
+            s == sig && valid_config(c, cplx)) {
+            *cfg = c;
+            *ms = t;
+            found = true;
+        }
+    }
+    fclose(f);
+    return found;
+}
+
+void cache_store(const char* path, uint64_t sig, const trbt_plan_config& c, double ms)
+{
+    FILE* f = fopen(path, "a");
+    if (!f) return;   // an unwritable cache only costs the next plan its tuning
+    fprintf(f, "trbt-tune-v1 %016llx %d %d %d %.6f\n", (unsigned long long)sig, c.strip_cols,
+            c.waves, c.block_stages, ms);
+    fclose(f);
+}
+
 int tune(trbt_plan& P)
+{
+    const char* cache = getenv("TRBT_TUNE_CACHE");
+    const uint64_t sig = (cache && *cache) ? plan_signature(P) : 0;
+    if (cache && *cache) {
+        trbt_plan_config c;
+        double ms = 0.0;
+        if (cache_lookup(cache, sig, P.cplx, &c, &ms)) {
+            P.cfg = c;
+            P.tuned_ms = ms;
+            return TRBT_SUCCESS;
+        }
+    }
+    const int rc = tune_by_timing(P);
+    if (!rc && cache && *cache) cache_store(cache, sig, P.cfg, P.tuned_ms);
+    return rc;
+}
+
+int tune_by_timing(trbt_plan& P)
 {
     // scratch copies of every Z, so that timing leaves the caller's data alone
     // (the last column is copied only up to row n: the caller's buffer may

@@ -549,9 +549,29 @@ __device__ inline bool wait_progress(int* prog, int idx, int need, unsigned* err
 // this wave read from it: when that already satisfies the wait, the LDS
 // round trip is skipped (the acquire that read `seen` also made visible
 // everything released before any smaller value).
+// Debug builds with TRBT_WAIT_JITTER (libtrbt_jitter.so, see build.py) delay
+// every wave by a pseudo-random 0..15 sleep quanta (64 clocks each) in front
+// of every wait, so that the hand-offs between waves run in many orders;
+// results must stay bitwise the same.  Release builds compile it away.
+__device__ inline void wait_jitter(int idx, int need)
+{
+#ifdef TRBT_WAIT_JITTER
+    uint32_t h = (uint32_t)wall_clock64() * 2654435761u ^ (uint32_t)(idx * 40503 + need * 977);
+    h ^= h >> 15;
+    h *= 2246822519u;
+    h ^= h >> 13;
+    const int r = __builtin_amdgcn_readfirstlane((int)(h & 15u));
+    for (int k = 0; k < r; ++k) __builtin_amdgcn_s_sleep(1);
+#else
+    (void)idx;
+    (void)need;
+#endif
+}
+
 __device__ inline bool wait_counter(int* ctr, int idx, int need, unsigned* err, int lane,
                                     int& seen)
 {
+    wait_jitter(idx, need);
     if (seen >= need) return true;
     unsigned spins = 0;
     int v;

@@ -338,3 +338,42 @@ def test_work_check_validation(T):
     f = C.c_int(7)
     assert T.lib().trbt_work_check(None, None, None) == -2
     assert T.lib().trbt_work_check(FAKE + 8, C.byref(f), None) == -1
+
+
+@pytest.mark.parametrize("fn", ["trans_ev_band_to_full_d", "trans_ev_band_to_full_z"])
+def test_band_to_full_validation_codes(T, fn):
+    """Argument errors of the band-to-full back-transformation come back
+    before any launch, one per argument position."""
+    f = getattr(T, fn)
+    ok = dict(n=100, nbw=16, nev=10, hh_v=FAKE, ldv=100, hh_tau=FAKE, Z=FAKE, ldz=100,
+              work=None, work_bytes=0)
+
+    def call(**kw):
+        a = dict(ok, **kw)
+        return f(a["n"], a["nbw"], a["nev"], a["hh_v"], a["ldv"], a["hh_tau"], a["Z"], a["ldz"],
+                 a["work"], a["work_bytes"], 0)
+
+    assert call(n=-1) == -1
+    assert call(nbw=0) == -2
+    assert call(nev=101) == -3
+    assert call(hh_v=None) == -4
+    assert call(ldv=99) == -5
+    assert call(hh_tau=None) == -6
+    assert call(Z=None) == -7
+    assert call(ldz=50) == -8
+    assert call(work=FAKE + 8) == -9
+    assert call() == -101                      # J > 0 needs the T workspace
+    # J == 0 (n <= nbw + 1) and nev == 0 are no-ops without a device
+    assert call(n=17, nbw=16, nev=3, ldv=17, ldz=17, hh_v=None, hh_tau=None) == 0
+    assert call(nev=0, hh_v=None, hh_tau=None, Z=None) == 0
+
+
+def test_band_to_full_workspace_size(T):
+    """A 256-byte header plus one 64 x 64 compact-WY factor per panel of 64
+    consecutive reflectors (J = n - nbw - 1 reflectors)."""
+    for n, nbw, cplx in ((100, 16, False), (1000, 64, True), (66, 64, False), (65, 64, False)):
+        J = max(n - nbw - 1, 0)
+        P = -(-J // 64)
+        expect = 0 if J == 0 else 256 + P * 64 * 64 * (16 if cplx else 8)
+        assert T.trbt_band_to_full_workspace_bytes(n, nbw, 5, cplx) == expect
+    assert T.trbt_band_to_full_workspace_bytes(1000, 64, 0, True) == 0

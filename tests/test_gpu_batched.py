@@ -373,3 +373,44 @@ def test_c4z_full_batch_sampled(oracle_mod):
         ref = oracle_mod.back_transform(Z, V, tau, nbw, cols=cols)
         assert _relerr(out[:, cols], ref) <= TOL, (i, n)
         assert np.array_equal(out, b.result(i)), (i, n)
+
+
+def test_tuning_cache_round_trip(oracle_mod, tmp_path, monkeypatch):
+    """TRBT_TUNE_CACHE: the first tuned plan of a problem set times the
+    candidates and appends one line; a second plan of the same shapes (other
+    buffers) takes the cached choice without timing; another shape set is a
+    miss.  Results are the same either way."""
+    import time
+    import paper_2002_10991_amd as T
+    torch = _torch()
+    cache = tmp_path / "tune.txt"
+    monkeypatch.setenv("TRBT_TUNE_CACHE", str(cache))
+    shapes = [(300, 32, 40), (520, 32, 100), (130, 16, 7)]
+    inputs = [_problem_inputs(n, nbw, nev, 7100 + i, oracle_mod)
+              for i, (n, nbw, nev) in enumerate(shapes)]
+    plans = []
+    for k in range(2):
+        batch = DeviceBatch(shapes)
+        batch.load(inputs)
+        print(f"[gpu] tuned plan {k}", flush=True)
+        t0 = time.perf_counter()
+        plan = T.BatchedPlan(batch.problems())
+        dt = time.perf_counter() - t0
+        plans.append((plan, batch, dt))
+        assert len(cache.read_text().splitlines()) == 1     # a hit appends nothing
+    (p1, b1, t1), (p2, b2, t2) = plans
+    cfg1, ms1 = p1.config
+    cfg2, ms2 = p2.config
+    assert cfg1 == cfg2 and ms2 == pytest.approx(ms1, rel=1e-5)
+    assert cache.read_text().startswith("trbt-tune-v1 ")
+    print(f"[gpu] tuned plan {t1:.3f} s, cached plan {t2:.3f} s, config {cfg1}", flush=True)
+    for plan, batch, _ in plans:
+        plan.run()
+        torch.cuda.synchronize()
+        assert plan.fault() == 0
+        _check_against_oracle(batch, inputs, oracle_mod)
+        plan.close()
+    other = DeviceBatch(shapes[:2])
+    other.load(inputs[:2])
+    T.BatchedPlan(other.problems()).close()
+    assert len(cache.read_text().splitlines()) == 2         # a new signature
