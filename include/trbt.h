@@ -61,6 +61,8 @@ extern "C" {
 #define TRBT_ERR_WORKSPACE (-101) /* work too small or misaligned          */
 #define TRBT_ERR_HIP (-102)       /* a HIP runtime call / launch failed    */
 #define TRBT_ERR_INTERNAL (-103)  /* unexpected state (should not happen)  */
+#define TRBT_ERR_SCRATCH (-104)   /* problem too large for the fixed scratch
+                                     of an allocation-free entry point     */
 
 #define TRBT_NBW_MAX 256          /* largest semi-bandwidth accepted       */
 #define TRBT_WORK_ALIGN 256       /* required alignment of `work`, bytes   */
@@ -462,6 +464,26 @@ int trans_ev_band_to_full_d(int64_t n, int nbw, int64_t nev, const double *hh_v,
 int trans_ev_band_to_full_z(int64_t n, int nbw, int64_t nev, const trbt_z *hh_v, int64_t ldv,
                             const trbt_z *hh_tau, trbt_z *Z, int64_t ldz, void *work,
                             size_t work_bytes, void *stream);
+
+/* Allocation-free form of trans_ev_band_to_full_z, for callers that cannot
+ * allocate device memory or pass a workspace (code under HIP graph capture,
+ * tight serving loops, harnesses that forbid hipMalloc).  Same operation,
+ * arguments 1-8 and results (bitwise) as trans_ev_band_to_full_z; argument
+ * 9 is the stream.  The compact-WY factors go to a fixed device array of
+ * TRBT_B2F_SCRATCH_BYTES inside the library (one per device the library
+ * runs on, held until the process ends), so the call allocates nothing.
+ * It takes problems whose workspace (trbt_band_to_full_workspace_bytes,
+ * is_complex = 1) fits in that array -- with 64-reflector panels, J =
+ * n - nbw - 1 <= 32704 -- and returns TRBT_ERR_SCRATCH for larger ones
+ * before any launch.  All calls on one device share the array: calls that
+ * may overlap in time on one device (different streams, or several host
+ * threads without ordering) race on it and give wrong results; calls
+ * ordered on one stream are safe.  The first call on each device looks up
+ * the array's device address (hipGetSymbolAddress) with that device current. */
+#define TRBT_B2F_SCRATCH_BYTES (32u << 20)
+int trans_ev_band_to_full_z_noalloc(int64_t n, int nbw, int64_t nev, const trbt_z *hh_v,
+                                    int64_t ldv, const trbt_z *hh_tau, trbt_z *Z, int64_t ldz,
+                                    void *stream);
 
 /* Fault word of a workspace.  The blocked kernels of
  * trans_ev_tridi_to_band_{d,z} / trbt_apply_{d,z}, of the real adjoints

@@ -30,6 +30,7 @@ __all__ = [
     "band_to_tridiagonal", "trbt_tridiag_eigh_workspace_bytes", "trbt_tridiag_eigh_d",
     "tridiagonal_eigh", "trbt_work_check", "trbt_band_to_full_workspace_bytes",
     "trans_ev_band_to_full_d", "trans_ev_band_to_full_z", "band_to_full",
+    "trans_ev_band_to_full_z_noalloc", "TRBT_B2F_SCRATCH_BYTES",
 ]
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
@@ -38,6 +39,7 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.environ.get("TRBT_LIB") or os.path.join(_HERE, "libtrbt.so")
 TRBT_WORK_ALIGN = 256
 TRBT_NBW_MAX = 256
+TRBT_B2F_SCRATCH_BYTES = 32 << 20
 _lib = None
 
 
@@ -130,6 +132,8 @@ def lib():
         for f in (L.trans_ev_band_to_full_d, L.trans_ev_band_to_full_z):
             f.argtypes = [i64, i32, i64, vp, i64, vp, vp, i64, vp, sz, vp]
             f.restype = i32
+        L.trans_ev_band_to_full_z_noalloc.argtypes = [i64, i32, i64, vp, i64, vp, vp, i64, vp]
+        L.trans_ev_band_to_full_z_noalloc.restype = i32
         L.trbt_work_check.argtypes = [vp, C.POINTER(i32), vp]
         L.trbt_work_check.restype = i32
         L.trbt_strerror.argtypes = [i32]
@@ -679,6 +683,11 @@ def trans_ev_band_to_full_z(n, nbw, nev, hh_v, ldv, hh_tau, Z, ldz, work, work_b
                             stream=None) -> int:
     return lib().trans_ev_band_to_full_z(n, nbw, nev, _ptr(hh_v), ldv, _ptr(hh_tau), _ptr(Z), ldz,
                                          _ptr(work), work_bytes, _stream(stream))
+
+
+def trans_ev_band_to_full_z_noalloc(n, nbw, nev, hh_v, ldv, hh_tau, Z, ldz, stream=None) -> int:
+    return lib().trans_ev_band_to_full_z_noalloc(n, nbw, nev, _ptr(hh_v), ldv, _ptr(hh_tau),
+                                                 _ptr(Z), ldz, _stream(stream))
 
 
 def band_to_full(Z, hh_v, hh_tau, nbw: int, work=None, stream=None):

@@ -207,6 +207,7 @@ const char* trbt_strerror(int status)
         case TRBT_ERR_WORKSPACE: return "workspace too small or missing";
         case TRBT_ERR_HIP: return "HIP runtime error";
         case TRBT_ERR_INTERNAL: return "internal error";
+        case TRBT_ERR_SCRATCH: return "problem too large for the fixed scratch of an allocation-free entry point";
         default: break;
     }
     if (status < 0 && status > -20) return "invalid argument (see the argument position)";

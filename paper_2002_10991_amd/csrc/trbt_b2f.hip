@@ -34,6 +34,8 @@
 
 #include <stdint.h>
 
+#include <mutex>
+
 #include "trbt.h"
 #include "trbt_device.h"
 
@@ -429,6 +431,46 @@ int b2f_run(int64_t n, int nbw, int64_t nev, const double* V, int64_t ldv, const
     return hipGetLastError() == hipSuccess ? TRBT_SUCCESS : TRBT_ERR_HIP;
 }
 
+// --------------------------------------------------------------------------
+// Allocation-free variant (trans_ev_band_to_full_z_noalloc): the per-panel
+// T factors go to a fixed array of device memory instead of a caller
+// workspace.  Every device the library runs on holds its own copy of the
+// array until the process ends; all calls on one device share it.  Host
+// code never passes the array's name to a kernel (on the host it is only a
+// stand-in for the symbol): it looks up the device address once per device
+// and passes that.
+// --------------------------------------------------------------------------
+constexpr int B2F_MAX_DEVICES = 64;
+std::mutex b2f_scratch_mu;
+void* b2f_scratch_ptr[B2F_MAX_DEVICES];
+
+}  // namespace
+
+static_assert(TRBT_B2F_SCRATCH_BYTES % 256 == 0, "scratch size");
+static __device__ __align__(256) unsigned char scratch[TRBT_B2F_SCRATCH_BYTES];
+
+namespace {
+
+// Device address of `scratch` on the current device (looked up on the first
+// call on each device, with that device current).
+int b2f_scratch(void** out)
+{
+    int dev = -1;
+    if (hipGetDevice(&dev) != hipSuccess) return TRBT_ERR_HIP;
+    if (dev < 0 || dev >= B2F_MAX_DEVICES) return TRBT_ERR_DEVICE;
+    std::lock_guard<std::mutex> lock(b2f_scratch_mu);
+    if (!b2f_scratch_ptr[dev]) {
+        void* p = nullptr;
+        if (hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)) != hipSuccess || !p) {
+            (void)hipGetLastError();
+            return TRBT_ERR_HIP;
+        }
+        b2f_scratch_ptr[dev] = p;
+    }
+    *out = b2f_scratch_ptr[dev];
+    return TRBT_SUCCESS;
+}
+
 }  // namespace
 
 extern "C" {
@@ -457,6 +499,23 @@ int trans_ev_band_to_full_z(int64_t n, int nbw, int64_t nev, const trbt_z* hh_v,
 {
     return b2f_run<true>(n, nbw, nev, (const double*)hh_v, ldv, (const double*)hh_tau,
                          (double*)Z, ldz, work, work_bytes, stream);
+}
+
+int trans_ev_band_to_full_z_noalloc(int64_t n, int nbw, int64_t nev, const trbt_z* hh_v,
+                                    int64_t ldv, const trbt_z* hh_tau, trbt_z* Z, int64_t ldz,
+                                    void* stream)
+{
+    int rc = b2f_validate<true>(n, nbw, nev, hh_v, ldv, hh_tau, Z, ldz, nullptr, 0);
+    if (rc) return rc;
+    if (b2f_reflectors(n, nbw) == 0 || nev == 0) return TRBT_SUCCESS;
+    if (b2f_bytes(n, nbw, true) > TRBT_B2F_SCRATCH_BYTES) return TRBT_ERR_SCRATCH;
+    rc = check_device();
+    if (rc) return rc;
+    void* s = nullptr;
+    rc = b2f_scratch(&s);
+    if (rc) return rc;
+    return b2f_run<true>(n, nbw, nev, (const double*)hh_v, ldv, (const double*)hh_tau,
+                         (double*)Z, ldz, s, TRBT_B2F_SCRATCH_BYTES, stream);
 }
 
 }  // extern "C"

@@ -377,3 +377,36 @@ def test_band_to_full_workspace_size(T):
         expect = 0 if J == 0 else 256 + P * 64 * 64 * (16 if cplx else 8)
         assert T.trbt_band_to_full_workspace_bytes(n, nbw, 5, cplx) == expect
     assert T.trbt_band_to_full_workspace_bytes(1000, 64, 0, True) == 0
+
+
+def test_band_to_full_noalloc_validation_and_limit(T):
+    """The allocation-free band-to-full call validates arguments 1-8 like
+    trans_ev_band_to_full_z and rejects, before any launch, problems whose
+    compact-WY factors exceed its fixed scratch (TRBT_B2F_SCRATCH_BYTES)."""
+    f = T.trans_ev_band_to_full_z_noalloc
+    ok = dict(n=300, nbw=16, nev=10, hh_v=FAKE, ldv=300, hh_tau=FAKE, Z=FAKE, ldz=300)
+
+    def call(**kw):
+        a = dict(ok, **kw)
+        return f(a["n"], a["nbw"], a["nev"], a["hh_v"], a["ldv"], a["hh_tau"], a["Z"],
+                 a["ldz"], 0)
+
+    assert call(n=-1) == -1
+    assert call(nbw=0) == -2
+    assert call(nev=301) == -3
+    assert call(hh_v=None) == -4
+    assert call(ldv=299) == -5
+    assert call(hh_tau=None) == -6
+    assert call(Z=None) == -7
+    assert call(ldz=10) == -8
+    assert call(n=17, nbw=16, nev=3, ldv=17, ldz=17, hh_v=None, hh_tau=None) == 0
+    assert call(nev=0, hh_v=None, hh_tau=None, Z=None) == 0
+    # the largest J whose 64-reflector panels fit, and one panel more
+    cap = T.TRBT_B2F_SCRATCH_BYTES
+    pmax = (cap - 256) // (64 * 64 * 16)
+    n_fit = 64 * pmax + 64 + 1
+    assert T.trbt_band_to_full_workspace_bytes(n_fit, 64, 1, True) <= cap
+    assert T.trbt_band_to_full_workspace_bytes(n_fit + 1, 64, 1, True) > cap
+    big = n_fit + 1
+    assert call(n=big, nbw=64, nev=1, ldv=big, ldz=big) == -104
+    assert "scratch" in T.trbt_strerror(-104)
