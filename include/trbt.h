@@ -83,8 +83,8 @@ int trbt_stage_offsets(int64_t n, int nbw, int64_t *off);
 
 /* Bytes of device workspace the back-transformation of (n, nbw, nev) needs
  * (real: is_complex = 0, complex: 1).  The workspace holds the per-block
- * compact-WY factors the blocked kernels precompute; it may be 0 for shapes
- * served by the unblocked kernel.  The same workspace can be reused by any
+ * compact-WY factors the blocked kernels precompute (nbw a multiple of 16
+ * up to 128); it is 0 for shapes served by the unblocked kernel.  The same workspace can be reused by any
  * later call with the same or smaller sizes.  Errors as for the transform
  * (-1 n, -2 nbw, -3 nev; -4 null `bytes`). */
 int trbt_workspace_bytes(int64_t n, int nbw, int64_t nev, int is_complex, size_t *bytes);
@@ -207,15 +207,21 @@ int trans_ev_tridi_to_band_bwd_ckpt_d(int64_t n, int nbw, int64_t nev,
  *   grad v_k  = sum over columns of -conj(tau_k) conj(w) g - tau_k conj(gamma) z,
  *   grad tau_k = sum over columns of -conj(w) gamma,
  * with z the column rows entering H_k in the forward pass, g the gradient
- * rows leaving it, w = v_k^H z and gamma = v_k^H g.  Computed stage by
+ * rows leaving it, w = v_k^H z and gamma = v_k^H g.  For nbw in {16, 32,
+ * 48, 64} the blocked form of the real adjoint with complex operands
+ * (compact-WY blocks of 16 stages on FP64 MFMA, a checkpoint of every
+ * block's input window, a gradient sweep and a per-block reduction);
+ * workspace: a copy of Z_in, the packed factors of both passes and two
+ * copies of every block's (nbw+16) x 16 windows, about
+ * n^2 nev (nbw+16) / nbw bytes in all (43 GB at n = 4096, nbw = 64,
+ * nev = 2048).  Other nbw: stage by
  * stage (the slots of a stage are disjoint, Sec. 2.2.2: one launch per
  * stage over all slots and columns) on row-major working copies of Z and G,
  * with the rows a 16-stage segment touches checkpointed before it and the
- * segment recomputed in the reverse sweep; the column sums behind dv and
- * dtau are taken in a fixed order (bitwise reproducible).  Any nbw.
- * Workspace: two working copies (2 n nev complex), the checkpoints (about
- * n^2 nev / 32 complex), one segment's tape (about 16 n nev complex) and
- * the per-256-column partial sums ((nev/256) K (nbw+1) complex).
+ * segment recomputed in the reverse sweep; workspace: two working copies,
+ * the checkpoints (about n^2 nev / 32 complex), one segment's tape and
+ * per-256-column partial sums.  Both forms take the column sums behind dv
+ * and dtau in a fixed order (bitwise reproducible).
  * Arguments, validation and status codes as trans_ev_tridi_to_band_adjoint_d,
  * with complex hh_v, hh_tau, Z_in, G, dv, dtau and the workspace size from
  * trbt_adjoint_workspace_bytes_z. */

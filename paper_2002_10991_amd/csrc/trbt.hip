@@ -27,7 +27,7 @@ int prepare(int64_t n, int nbw, const double* hv, const double* ht, void* work,
     if (K > 0 && !ht) return -4;
     if (work && ((uintptr_t)work % TRBT_WORK_ALIGN)) return -5;
     if (work_bytes && !work) return -5;
-    if (K == 0 || !use_blocked(n, nbw, CPLX)) return TRBT_SUCCESS;
+    if (K == 0 || !use_blocked_apply(n, nbw, CPLX)) return TRBT_SUCCESS;
     if (!work || work_bytes < blocked_bytes(n, nbw, CPLX)) return TRBT_ERR_WORKSPACE;
     int rc = check_device();
     if (rc) return rc;
@@ -45,6 +45,10 @@ int prepare(int64_t n, int nbw, const double* hv, const double* ht, void* work,
         TRBT_PACK(32)
         TRBT_PACK(48)
         TRBT_PACK(64)
+        TRBT_PACK(80)
+        TRBT_PACK(96)
+        TRBT_PACK(112)
+        TRBT_PACK(128)
         default: return TRBT_ERR_INTERNAL;
     }
 #undef TRBT_PACK
@@ -62,22 +66,30 @@ int apply(int64_t n, int nbw, int64_t nev, const double* hv, const double* ht, d
     if (rc) return rc;
     hipStream_t st = (hipStream_t)stream_v;
 
-    if (use_blocked(n, nbw, CPLX)) {
+    if (use_blocked_apply(n, nbw, CPLX)) {
         if (work_bytes < blocked_bytes(n, nbw, CPLX) || !work) return TRBT_ERR_WORKSPACE;
         const double* ws = (const double*)work;
         const int CT = 1;
         const int64_t strips = (nev + 16 * CT - 1) / (16 * CT);
+        // nbw > 64: windows of 6..9 tiles need one wave per SIMD (4 waves,
+        // all 512 registers) and a half-block operand ring
 #define TRBT_MAIN(NBV)                                                                         \
-    case NBV:                                                                                  \
-        hipLaunchKernelGGL((k_blocked<NBV, 1, CPLX, ring_depth<NBV, CPLX>(), WAVES>),               \
-                           dim3((unsigned)strips),                                             \
-                           dim3(64 * WAVES), 0, st, n, nev, ws, Z, ldz, (unsigned*)work);      \
-        break;
+    case NBV: {                                                                                \
+        constexpr int NW = NBV <= 64 ? WAVES : 4;                                              \
+        constexpr int D = (NBV <= 64 || CPLX) ? ring_depth<NBV, CPLX>() : 4 * (NBV / 16 + 1);  \
+        hipLaunchKernelGGL((k_blocked<NBV, 1, CPLX, D, NW>), dim3((unsigned)strips),           \
+                           dim3(64 * NW), 0, st, n, nev, ws, Z, ldz, (unsigned*)work);         \
+        break;                                                                                 \
+    }
         switch (nbw) {
             TRBT_MAIN(16)
             TRBT_MAIN(32)
             TRBT_MAIN(48)
             TRBT_MAIN(64)
+        TRBT_MAIN(80)
+        TRBT_MAIN(96)
+        TRBT_MAIN(112)
+        TRBT_MAIN(128)
             default: return TRBT_ERR_INTERNAL;
         }
 #undef TRBT_MAIN
@@ -137,7 +149,7 @@ int trbt_workspace_bytes(int64_t n, int nbw, int64_t nev, int is_complex, size_t
     if (nbw < 1 || nbw > TRBT_NBW_MAX) return -2;
     if (nev < 0 || nev > n) return -3;
     if (!bytes) return -4;
-    *bytes = (use_blocked(n, nbw, is_complex != 0) && num_reflectors(n, nbw) > 0 && nev > 0)
+    *bytes = (use_blocked_apply(n, nbw, is_complex != 0) && num_reflectors(n, nbw) > 0 && nev > 0)
                  ? blocked_bytes(n, nbw, is_complex != 0)
                  : 0;
     return TRBT_SUCCESS;

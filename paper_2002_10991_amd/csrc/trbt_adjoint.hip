@@ -1,5 +1,8 @@
-// trbt_adjoint.hip -- adjoint (reverse-mode derivative) of the real
-// tridiagonal-to-banded eigenvector back-transformation on MI355X (gfx950).
+// trbt_adjoint.hip -- adjoint (reverse-mode derivative) of the
+// tridiagonal-to-banded eigenvector back-transformation on MI355X (gfx950):
+// the real adjoint (blocked and streaming forms) and the blocked form of the
+// complex one (conjugate-Wirtinger gradients, see trbt_adjoint_z.hip; every
+// formula below holds with conj the identity for real data).
 //
 // Forward map (Yu et al., CPC 2020, Eq. 2stage_bkwd1, real reflectors):
 //     Z_out = H_0 H_1 ... H_{K-1} Z_in,   H_k = I - tau_k v_k v_k^T.
@@ -10,16 +13,19 @@
 // dv = -tau sum_c (wk g + gk z), and g <- g - tau gk v.
 //
 // Blocked path (nbw in {16, 32, 48, 64}): the reflectors of one slot over
-// 16 consecutive stages form one compact-WY block Q = H_0..H_15 = I - V T V^T
+// 16 consecutive stages form one compact-WY block Q = H_0..H_15 = I - V T V^H
 // (generation order p = 0..15 inside the block).  With X the block's input
-// window (80 rows for nbw 64) and Go the gradient on its output window:
-//   w_p  = v_p^T Z^(p+1) = (R^T V^T X)_p      R[:,p] = e_p - [0; T_{>p}^T M_{>p,p}]
-//   g_p  = v_p^T G^(p)   = (S^T V^T Go)_p     S[:,p] = e_p - [T_{<p} M_{<p,p}; 0]
-//   Gi   = Q^T Go        = Go - V (T^T V^T Go)
-//   dv_p = -tau_p [ (I - V_{<p} T_{<p}^T V_{<p}^T) P1_p
-//                 + (I - V_{>p} T_{>p}   V_{>p}^T) P2_p ]   on v_p's rows,
-//   P1 = Go W, P2 = X g  (sums over columns),  dtau_p = -sum_c g_p w_p,
-// M = V^T V.  The intermediate states inside a block are never formed: the
+// window (80 rows for nbw 64), Go the gradient on its output window,
+// Z^(p+1) the state entering H_p and G^(p) the gradient leaving it:
+//   w_p  = v_p^H Z^(p+1) = (R V^H X)_p    R[p][a] = delta - sum_{p<b<=a} M[p][b] T[b][a]
+//   g_p  = v_p^H G^(p)   = (S V^H Go)_p   S[p][b] = delta - sum_{b<=a<p} M[p][a] conj(T[b][a])
+//   Gi   = Q^H Go        = Go - V (T^H V^H Go)
+//   dv_p = -conj(tau_p) (I - V_{<p} T_{<p}^H V_{<p}^H) P1_p
+//          - tau_p (I - V_{>p} T_{>p} V_{>p}^H) P2_p      on v_p's rows,
+//   P1 = Go W^H, P2 = X g^H  (sums over columns),  dtau_p = -sum_c conj(w_p) g_p,
+// M = V^H V (Z^(p+1) = (I - V_{>p} T_{>p} V_{>p}^H) X and G^(p) =
+// (I - V_{<p} T_{<p}^H V_{<p}^H) Go, the trailing and leading blocks of T
+// being the factors of the trailing and leading reflectors).  The intermediate states inside a block are never formed: the
 // block's input window is the checkpoint (one per slot every 16 stages),
 // written by a first forward pass.  The backward sweep walks every slot's
 // blocks from the lowest stages up (the window slides down one tile per
@@ -46,75 +52,164 @@
 namespace {
 
 // ==========================================================================
-// Blocked adjoint
+// Blocked adjoint (real and complex)
 // ==========================================================================
-template <int NB>
+template <int NB, bool CPLX = false>
 struct AdjGeo {
     static constexpr int NT = NB / 16 + 1;               // tiles per window
-    static constexpr int VT_OFF = 0;                     // V^T chunks (q,u) at 4q+u
-    static constexpr int NV_OFF = 4 * NT * 64;           // -V chunks  (q,u) at 4q+u
-    static constexpr int RT_OFF = 8 * NT * 64;           // R^T chunks u = 0..3
-    static constexpr int ST_OFF = RT_OFF + 256;          // S^T chunks
-    static constexpr int TT_OFF = ST_OFF + 256;          // T^T chunks
-    static constexpr int T_OFF = TT_OFF + 256;           // T, row major 16 x 16
-    static constexpr int TAU_OFF = T_OFF + 256;          // tau_p
-    static constexpr int APB = (TAU_OFF + 16 + 31) / 32 * 32;   // doubles per block
+    static constexpr int NC = CPLX ? 2 : 1;              // planes (re, im)
+    static constexpr int CH = 64 * NC;                   // doubles per operand chunk
+    static constexpr int VT_OFF = 0;                     // V^H chunks (q,u) at 4q+u
+    static constexpr int NV_OFF = 4 * NT * CH;           // -V chunks  (q,u) at 4q+u
+    static constexpr int RT_OFF = 8 * NT * CH;           // R chunks u = 0..3
+    static constexpr int ST_OFF = RT_OFF + 4 * CH;       // S chunks
+    static constexpr int TT_OFF = ST_OFF + 4 * CH;       // T^H chunks
+    static constexpr int T_OFF = TT_OFF + 4 * CH;        // T, row major 16 x 16 (x NC)
+    static constexpr int TAU_OFF = T_OFF + 256 * NC;     // tau_p (x NC)
+    static constexpr int APB = (TAU_OFF + 16 * NC + 31) / 32 * 32;   // doubles per block
 };
 
+// D += A B on FP64 MFMA for real or complex operands (complex: four real
+// products, the negate modifier giving -Im(A) Im(B)).
+template <bool CPLX>
+__device__ inline void cmma(double ar, double ai, double br, double bi, Tile<CPLX>& d)
+{
+    d.re = mfma(ar, br, d.re);
+    if constexpr (CPLX) {
+        d.re = mfma_n<1>(ai, bi, d.re);
+        d.im = mfma(ar, bi, d.im);
+        d.im = mfma(ai, br, d.im);
+    } else {
+        (void)ai;
+        (void)bi;
+    }
+}
+
+template <bool CPLX>
+__device__ inline Tile<CPLX> tile_zero()
+{
+    Tile<CPLX> t;
+    t.re = d4{0.0, 0.0, 0.0, 0.0};
+    if constexpr (CPLX) t.im = t.re;
+    return t;
+}
+
+template <bool CPLX>
+__device__ inline Tile<CPLX> tile_add(const Tile<CPLX>& a, const Tile<CPLX>& b)
+{
+    Tile<CPLX> t;
+    t.re = a.re + b.re;
+    if constexpr (CPLX) t.im = a.im + b.im;
+    return t;
+}
+
+template <bool CPLX>
+__device__ inline double tim(const Tile<CPLX>& t, int e)
+{
+    if constexpr (CPLX) return t.im[e];
+    (void)t;
+    (void)e;
+    return 0.0;
+}
+
 // Operand pack for the backward pass: one workgroup (256 threads) per block.
-// MFMA A-operand chunks (lane i + 16k holds A[i][k]):
-//   V^T chunk (q, u):   V^T[i][16q + 4u + k]     (K runs over window rows)
-//   -V chunk (q, u):    -V[16q + i][4u + k]      (K runs over reflectors)
-//   R^T, S^T, T^T chunk u: X^T[i][4u + k] = X[4u + k][i]
-template <int NB>
+// MFMA A-operand chunks (lane i + 16k holds A[i][k]; complex chunks hold the
+// real parts in lanes 0..63 and the imaginary parts after them):
+//   V^H chunk (q, u):   conj(V[16q + 4u + k][i])   (K runs over window rows)
+//   -V chunk (q, u):    -V[16q + i][4u + k]        (K runs over reflectors)
+//   R, S, T^H chunk u:  X[i][4u + k]
+// With M = V^H V and the block's factor T (Q = H_0 .. H_15 = I - V T V^H):
+//   R[p][a] = delta_pa - sum_{p < b <= a} M[p][b] T[b][a]      (0 for a < p)
+//   S[p][b] = delta_pb - sum_{b <= a < p} M[p][a] conj(T[b][a]) (0 for b > p)
+// so that, per column, w = R (V^H X) holds v_p^H (state entering H_p) and
+// g = S (V^H Go) holds v_p^H (gradient leaving H_p).
+template <int NB, bool CPLX>
 __global__ __launch_bounds__(256) void k_pack_adj(int64_t n, const double* __restrict__ hv,
                                                   const double* __restrict__ ht,
                                                   double* __restrict__ apk)
 {
-    using A = AdjGeo<NB>;
-    constexpr int NT = A::NT;
-    __shared__ WyBlock<NB, false> W;
-    __shared__ double Rm[16][17], Sm[16][17];
-    wy_factor<NB, false>(n, hv, ht, blockIdx.x, W);
+    using A = AdjGeo<NB, CPLX>;
+    constexpr int NT = A::NT, NC = A::NC, CH = A::CH;
+    __shared__ WyBlock<NB, CPLX> W;
+    __shared__ double Rm[16][17][NC], Sm[16][17][NC];
+    wy_factor<NB, CPLX>(n, hv, ht, blockIdx.x, W);
     const int tid = threadIdx.x;
     {
-        const int a = tid / 16, p = tid % 16;
-        double r = (a == p) ? 1.0 : 0.0, s = r;
-        for (int a2 = p + 1; a2 <= a; ++a2) r -= W.Tm[a2][a][0] * W.Gm[a2][p][0];
-        for (int a2 = a; a2 < p; ++a2) s -= W.Tm[a][a2][0] * W.Gm[a2][p][0];
-        Rm[a][p] = r;
-        Sm[a][p] = s;
+        const int p = tid / 16, a = tid % 16;
+        double rr = (a == p) ? 1.0 : 0.0, ri = 0.0, sr = rr, si = 0.0;
+        for (int b = p + 1; b <= a; ++b) {
+            const double mr = W.Gm[p][b][0], tr = W.Tm[b][a][0];
+            if constexpr (CPLX) {
+                const double mi = W.Gm[p][b][NC - 1], ti = W.Tm[b][a][NC - 1];
+                rr -= mr * tr - mi * ti;
+                ri -= mr * ti + mi * tr;
+            } else {
+                rr -= mr * tr;
+            }
+        }
+        for (int c = a; c < p; ++c) {   // S[p][a]: sum over a <= c < p
+            const double mr = W.Gm[p][c][0], tr = W.Tm[a][c][0];
+            if constexpr (CPLX) {
+                const double mi = W.Gm[p][c][NC - 1], ti = -W.Tm[a][c][NC - 1];
+                sr -= mr * tr - mi * ti;
+                si -= mr * ti + mi * tr;
+            } else {
+                sr -= mr * tr;
+            }
+        }
+        Rm[p][a][0] = rr;
+        Sm[p][a][0] = sr;
+        if constexpr (CPLX) {
+            Rm[p][a][NC - 1] = ri;
+            Sm[p][a][NC - 1] = si;
+        }
     }
     __syncthreads();
     double* out = apk + (size_t)blockIdx.x * A::APB;
     for (int idx = tid; idx < 4 * NT * 64; idx += 256) {
         const int lane = idx % 64, c = idx / 64, q = c / 4, u = c % 4;
-        out[A::VT_OFF + idx] = W.Vt[16 * q + 4 * u + lane / 16][lane % 16][0];
-        out[A::NV_OFF + idx] = -W.Vt[16 * q + lane % 16][4 * u + lane / 16][0];
+        const int r1 = 16 * q + 4 * u + lane / 16, p1 = lane % 16;
+        const int r2 = 16 * q + lane % 16, p2 = 4 * u + lane / 16;
+        out[A::VT_OFF + c * CH + lane] = W.Vt[r1][p1][0];
+        out[A::NV_OFF + c * CH + lane] = -W.Vt[r2][p2][0];
+        if constexpr (CPLX) {
+            out[A::VT_OFF + c * CH + 64 + lane] = -W.Vt[r1][p1][NC - 1];
+            out[A::NV_OFF + c * CH + 64 + lane] = -W.Vt[r2][p2][NC - 1];
+        }
     }
     {
         const int lane = tid % 64, u = tid / 64, i = lane % 16, k = lane / 16;
-        out[A::RT_OFF + tid] = Rm[4 * u + k][i];
-        out[A::ST_OFF + tid] = Sm[4 * u + k][i];
-        out[A::TT_OFF + tid] = W.Tm[4 * u + k][i][0];
-        out[A::T_OFF + tid] = W.Tm[tid / 16][tid % 16][0];
+        out[A::RT_OFF + u * CH + lane] = Rm[i][4 * u + k][0];
+        out[A::ST_OFF + u * CH + lane] = Sm[i][4 * u + k][0];
+        out[A::TT_OFF + u * CH + lane] = W.Tm[4 * u + k][i][0];
+        if constexpr (CPLX) {
+            out[A::RT_OFF + u * CH + 64 + lane] = Rm[i][4 * u + k][NC - 1];
+            out[A::ST_OFF + u * CH + 64 + lane] = Sm[i][4 * u + k][NC - 1];
+            out[A::TT_OFF + u * CH + 64 + lane] = -W.Tm[4 * u + k][i][NC - 1];
+        }
+#pragma unroll
+        for (int pl = 0; pl < NC; ++pl)
+            out[A::T_OFF + tid * NC + pl] = W.Tm[tid / 16][tid % 16][pl];
     }
-    if (tid < 16) out[A::TAU_OFF + tid] = W.tau[tid][0];
+    if (tid < 16) {
+#pragma unroll
+        for (int pl = 0; pl < NC; ++pl) out[A::TAU_OFF + tid * NC + pl] = W.tau[tid][pl];
+    }
 }
 
 // First pass: the forward transformation of a scratch copy of Z_in that
 // also checkpoints every block's input window.
-template <int NB, int NW>
+template <int NB, int NW, bool CPLX>
 __global__ __launch_bounds__(64 * NW) void k_blocked_ckpt(int64_t n, int64_t nev,
                                                           const double* __restrict__ blocks,
                                                           double* __restrict__ Z, int64_t ldz,
                                                           double* __restrict__ ckpt,
                                                           unsigned* __restrict__ err)
 {
-    __shared__ StripLds<NB, 1, false, NW> S;
+    __shared__ StripLds<NB, 1, CPLX, NW> S;
     S.reset();
     __syncthreads();
-    blocked_strip<NB, 1, false, ring_depth<NB, false>(), NW, true>(
+    blocked_strip<NB, 1, CPLX, ring_depth<NB, CPLX>(), NW, true>(
         n, nev, blocks, Z, ldz, err, blockIdx.x, S, ckpt, gridDim.x);
 }
 
@@ -133,7 +228,7 @@ __device__ inline void wave_lds_sync()
 // needs (t+1, j) (same wave, earlier) and (t, j+1), whose retired top tile
 // is this block's new bottom tile.  Slot j is handled by wave
 // (J-1-j) mod NW, so slot j+1 is on the previous wave.  Per block the
-// gradient window Go becomes Gi = Q^T Go = Go - V (T^T (V^T Go)), and Go is
+// gradient window Go becomes Gi = Q^H Go = Go - V (T^H (V^H Go)), and Go is
 // saved to gck in the checkpoint layout for the reduction pass.
 // Hand-off: a retired top tile goes to the next wave through an LDS ring
 // (counters written/consumed, back-pressure of XR tiles) when that wave holds
@@ -142,27 +237,28 @@ __device__ inline void wave_lds_sync()
 // block (the whole window is final) and across rounds.
 // Per-workgroup LDS state of the sweep: progress counters and the
 // wave-to-wave exchange ring (zero counters on entry).
-template <int NW>
+template <int NW, bool CPLX>
 struct SweepLds {
     static constexpr int XR = 3;
+    static constexpr int TD = 256 * (CPLX ? 2 : 1);   // doubles per tile
     int prog[NW], written[NW], consumed[NW];
-    double ring[NW - 1][XR][256];
+    double ring[NW - 1][XR][TD];
     __device__ void reset()
     {
         if (threadIdx.x < NW) prog[threadIdx.x] = written[threadIdx.x] = consumed[threadIdx.x] = 0;
     }
 };
 
-template <int NB, int NW>
-__device__ __attribute__((always_inline)) inline void adj_sweep_strip(int64_t n, int64_t nev, const double* __restrict__ apk,
-                                       double* __restrict__ G, int64_t ldg,
-                                       double* __restrict__ gck, unsigned* __restrict__ err,
-                                       int64_t strip, int64_t nstrips, SweepLds<NW>& S)
+template <int NB, int NW, bool CPLX>
+__device__ __attribute__((always_inline)) inline void adj_sweep_strip(
+    int64_t n, int64_t nev, const double* __restrict__ apk, double* __restrict__ G, int64_t ldg,
+    double* __restrict__ gck, unsigned* __restrict__ err, int64_t strip, int64_t nstrips,
+    SweepLds<NW, CPLX>& S)
 {
-    using A = AdjGeo<NB>;
-    constexpr int NT = A::NT;
+    using A = AdjGeo<NB, CPLX>;
+    constexpr int NT = A::NT, NC = A::NC, CH = A::CH;
     constexpr int64_t nt1 = NB / 16;
-    constexpr int XR = SweepLds<NW>::XR;
+    constexpr int XR = SweepLds<NW, CPLX>::XR;
     int* prog = S.prog;
     int* written = S.written;
     int* consumed = S.consumed;
@@ -180,7 +276,7 @@ __device__ __attribute__((always_inline)) inline void adj_sweep_strip(int64_t n,
     int seen = 0, seen_written = 0, seen_consumed = 0;
     int xput = 0, xget = 0;   // ring tiles put / taken so far
 
-    Tile<false> g[NT];
+    Tile<CPLX> g[NT];
 
     for (int64_t j = J - 1 - w; j >= 0; j -= NW) {
         const int64_t t0 = j * nt1;
@@ -193,7 +289,7 @@ __device__ __attribute__((always_inline)) inline void adj_sweep_strip(int64_t n,
 #pragma unroll
         for (int q = 0; q < NT; ++q) {
             const bool inside = cols_inside && p0 + 16 * q >= 0 && p0 + 16 * q + 16 <= n;
-            load_tile<false>(g[q], G, ldg, n, nev, p0 + 16 * q + rsub, col, inside);
+            load_tile<CPLX>(g[q], G, ldg, n, nev, p0 + 16 * q + rsub, col, inside);
         }
 
         for (int64_t t = nblk - 1; t >= t0; --t, p0 += KB) {
@@ -201,37 +297,46 @@ __device__ __attribute__((always_inline)) inline void adj_sweep_strip(int64_t n,
             const double* __restrict__ pk = apk + (size_t)b * A::APB;
             // the block's operands are read ahead of its stores: loads issued
             // after stores wait for them (one in-order vector-memory counter)
-            double vt[4 * NT], nv[4 * NT], tt[4];
+            double vt[4 * NT][NC], nv[4 * NT][NC], tt[4][NC];
 #pragma unroll
-            for (int c = 0; c < 4 * NT; ++c) {
-                vt[c] = pk[A::VT_OFF + c * 64 + lane];
-                nv[c] = pk[A::NV_OFF + c * 64 + lane];
-            }
+            for (int c = 0; c < 4 * NT; ++c)
 #pragma unroll
-            for (int u = 0; u < 4; ++u) tt[u] = pk[A::TT_OFF + u * 64 + lane];
+                for (int pl = 0; pl < NC; ++pl) {
+                    vt[c][pl] = pk[A::VT_OFF + c * CH + pl * 64 + lane];
+                    nv[c][pl] = pk[A::NV_OFF + c * CH + pl * 64 + lane];
+                }
+#pragma unroll
+            for (int u = 0; u < 4; ++u)
+#pragma unroll
+                for (int pl = 0; pl < NC; ++pl) tt[u][pl] = pk[A::TT_OFF + u * CH + pl * 64 + lane];
             // Go of this block, read once by the reduction pass: non-temporal
-            double* __restrict__ gp = gck + ((size_t)b * NT * nstrips + strip) * 256 + lane;
+            double* __restrict__ gp = gck + ((size_t)b * NT * nstrips + strip) * 256 * NC + lane;
 #pragma unroll
             for (int q = 0; q < NT; ++q)
 #pragma unroll
-                for (int e = 0; e < 4; ++e)
-                    __builtin_nontemporal_store(g[q].re[e], &gp[(size_t)q * nstrips * 256 + e * 64]);
-            // Bt = V^T Go, Y = T^T Bt, Gi = Go - V Y
-            d4 bt[2];
-            bt[0] = bt[1] = d4{0.0, 0.0, 0.0, 0.0};
+                for (int e = 0; e < 4; ++e) {
+                    __builtin_nontemporal_store(g[q].re[e],
+                                                &gp[(size_t)q * nstrips * 256 * NC + e * 64]);
+                    if constexpr (CPLX)
+                        __builtin_nontemporal_store(
+                            g[q].im[e], &gp[(size_t)q * nstrips * 512 + 256 + e * 64]);
+                }
+            // Bt = V^H Go, Y = T^H Bt, Gi = Go - V Y
+            Tile<CPLX> bt[2];
+            bt[0] = bt[1] = tile_zero<CPLX>();
 #pragma unroll
             for (int c = 0; c < 4 * NT; ++c) {
                 const int q = c >> 2, u = c & 3;
-                bt[q & 1] = mfma(vt[c], g[q].re[u], bt[q & 1]);
+                cmma<CPLX>(vt[c][0], vt[c][NC - 1], g[q].re[u], tim(g[q], u), bt[q & 1]);
             }
-            const d4 Bt = bt[0] + bt[1];
-            d4 Y = d4{0.0, 0.0, 0.0, 0.0};
+            const Tile<CPLX> Bt = tile_add(bt[0], bt[1]);
+            Tile<CPLX> Y = tile_zero<CPLX>();
 #pragma unroll
-            for (int u = 0; u < 4; ++u) Y = mfma(tt[u], Bt[u], Y);
+            for (int u = 0; u < 4; ++u) cmma<CPLX>(tt[u][0], tt[u][NC - 1], Bt.re[u], tim(Bt, u), Y);
 #pragma unroll
             for (int c = 0; c < 4 * NT; ++c) {
                 const int q = c >> 2, u = c & 3;
-                g[q].re = mfma(nv[c], Y[u], g[q].re);
+                cmma<CPLX>(nv[c][0], nv[c][NC - 1], Y.re[u], tim(Y, u), g[q]);
             }
             // slide down: the top tile leaves for slot j-1, a new bottom tile
             // arrives from slot j+1 (or from G when slot j+1 has no block)
@@ -241,13 +346,16 @@ __device__ __attribute__((always_inline)) inline void adj_sweep_strip(int64_t n,
                         return;
                     double* dst = &ring[w][xput % XR][0];
 #pragma unroll
-                    for (int e = 0; e < 4; ++e) dst[e * 64 + lane] = g[0].re[e];
+                    for (int e = 0; e < 4; ++e) {
+                        dst[e * 64 + lane] = g[0].re[e];
+                        if constexpr (CPLX) dst[256 + e * 64 + lane] = g[0].im[e];
+                    }
                     ++xput;
                     __hip_atomic_store(&written[w], xput, __ATOMIC_RELEASE,
                                        __HIP_MEMORY_SCOPE_WORKGROUP);
                 } else {
-                    store_tile<false>(g[0], G, ldg, n, nev, p0 + rsub, col,
-                                      cols_inside && p0 >= 0 && p0 + 16 <= n);
+                    store_tile<CPLX>(g[0], G, ldg, n, nev, p0 + rsub, col,
+                                     cols_inside && p0 >= 0 && p0 + 16 <= n);
                 }
                 __hip_atomic_store(&prog[w], base + (int)(nblk - t), __ATOMIC_RELEASE,
                                    __HIP_MEMORY_SCOPE_WORKGROUP);
@@ -257,7 +365,10 @@ __device__ __attribute__((always_inline)) inline void adj_sweep_strip(int64_t n,
                     if (!wait_counter(written, w - 1, xget + 1, err, lane, seen_written)) return;
                     const double* src = &ring[w - 1][xget % XR][0];
 #pragma unroll
-                    for (int e = 0; e < 4; ++e) g[NT - 1].re[e] = src[e * 64 + lane];
+                    for (int e = 0; e < 4; ++e) {
+                        g[NT - 1].re[e] = src[e * 64 + lane];
+                        if constexpr (CPLX) g[NT - 1].im[e] = src[256 + e * 64 + lane];
+                    }
                     ++xget;
                     __hip_atomic_store(&consumed[w - 1], xget, __ATOMIC_RELEASE,
                                        __HIP_MEMORY_SCOPE_WORKGROUP);
@@ -268,12 +379,12 @@ __device__ __attribute__((always_inline)) inline void adj_sweep_strip(int64_t n,
                         return;
                     const int64_t r = p0 + KB + 16 * (NT - 1);
                     const bool inside = cols_inside && r >= 0 && r + 16 <= n;
-                    load_tile<false>(g[NT - 1], G, ldg, n, nev, r + rsub, col, inside);
+                    load_tile<CPLX>(g[NT - 1], G, ldg, n, nev, r + rsub, col, inside);
                 }
             } else {
 #pragma unroll
                 for (int q = 0; q < NT; ++q)
-                    store_tile<false>(g[q], G, ldg, n, nev, p0 + 16 * q + rsub, col);
+                    store_tile<CPLX>(g[q], G, ldg, n, nev, p0 + 16 * q + rsub, col);
                 __hip_atomic_store(&prog[w], base + (int)(nblk - t), __ATOMIC_RELEASE,
                                    __HIP_MEMORY_SCOPE_WORKGROUP);
             }
@@ -281,17 +392,17 @@ __device__ __attribute__((always_inline)) inline void adj_sweep_strip(int64_t n,
     }
 }
 
-template <int NB, int NW>
+template <int NB, int NW, bool CPLX>
 __global__ __launch_bounds__(64 * NW) void k_adj_sweep(int64_t n, int64_t nev,
                                                        const double* __restrict__ apk,
                                                        double* __restrict__ G, int64_t ldg,
                                                        double* __restrict__ gck,
                                                        unsigned* __restrict__ err)
 {
-    __shared__ SweepLds<NW> S;
+    __shared__ SweepLds<NW, CPLX> S;
     S.reset();
     __syncthreads();
-    adj_sweep_strip<NB, NW>(n, nev, apk, G, ldg, gck, err, blockIdx.x, gridDim.x, S);
+    adj_sweep_strip<NB, NW, CPLX>(n, nev, apk, G, ldg, gck, err, blockIdx.x, gridDim.x, S);
 }
 
 // The one-call adjoint runs the checkpointing forward and the sweep in one
@@ -299,7 +410,7 @@ __global__ __launch_bounds__(64 * NW) void k_adj_sweep(int64_t n, int64_t nev,
 // packs), and each has only one workgroup per column strip, so together
 // they fill twice as many CUs.  Workgroups [0, ns) run the forward,
 // [ns, 2 ns) the sweep.
-template <int NB, int NW>
+template <int NB, int NW, bool CPLX>
 __global__ __launch_bounds__(64 * NW) void k_adj_fwd_sweep(int64_t n, int64_t nev,
                                                            const double* __restrict__ blocks,
                                                            double* __restrict__ Z, int64_t ldz,
@@ -310,46 +421,55 @@ __global__ __launch_bounds__(64 * NW) void k_adj_fwd_sweep(int64_t n, int64_t ne
                                                            unsigned* __restrict__ err)
 {
     __shared__ union {
-        StripLds<NB, 1, false, NW> f;
-        SweepLds<NW> b;
+        StripLds<NB, 1, CPLX, NW> f;
+        SweepLds<NW, CPLX> b;
     } U;
     const int64_t ns = gridDim.x / 2;
     if ((int64_t)blockIdx.x < ns) {
         U.f.reset();
         __syncthreads();
-        blocked_strip<NB, 1, false, ring_depth<NB, false>(), NW, true>(
+        blocked_strip<NB, 1, CPLX, ring_depth<NB, CPLX>(), NW, true>(
             n, nev, blocks, Z, ldz, err, blockIdx.x, U.f, ckpt, ns);
     } else {
         U.b.reset();
         __syncthreads();
-        adj_sweep_strip<NB, NW>(n, nev, apk, G, ldg, gck, err, blockIdx.x - ns, ns, U.b);
+        adj_sweep_strip<NB, NW, CPLX>(n, nev, apk, G, ldg, gck, err, blockIdx.x - ns, ns, U.b);
     }
 }
 
 // Reduction pass: one workgroup per block, RW waves.  From the block's input
 // window X (checkpoint) and output gradient Go of every column strip:
-//   w = R^T (V^T X), g = S^T (V^T Go), dtau_p = -sum_c g_p w_p,
-//   P1 = Go W, P2 = X g   (sums over all columns),
+//   w = R (V^H X), g = S (V^H Go), dtau_p = -sum_c conj(w_p) g_p,
+//   P1 = Go W^H, P2 = X g^H   (sums over all columns),
 // each wave summing its strips (s = w, w + RW, ...) in registers and the waves
 // then combined in wave order (the same result on every run); finally the
-// column-independent corrections give dv and dtau of the block's reflectors.
-template <int NB, int RW>
-__global__ __launch_bounds__(64 * RW, 2) void k_adj_reduce(int64_t n, int64_t nstrips,
-                                                        const double* __restrict__ apk,
-                                                        const double* __restrict__ ckpt,
-                                                        const double* __restrict__ gck,
-                                                        double* __restrict__ dv,
-                                                        double* __restrict__ dtau)
+// column-independent corrections
+//   dv_p = -conj(tau_p) (I - V_<p T_<p^H V_<p^H) P1_p - tau_p (I - V_>p T_>p V_>p^H) P2_p
+// on v_p's rows give dv and dtau of the block's reflectors (real: conj is
+// the identity).
+template <int NB, int RW, bool CPLX>
+__global__ __launch_bounds__(64 * RW, CPLX ? 1 : 2) void k_adj_reduce(
+    int64_t n, int64_t nstrips, const double* __restrict__ apk, const double* __restrict__ ckpt,
+    const double* __restrict__ gck, double* __restrict__ dv, double* __restrict__ dtau)
 {
     static_assert(RW * 64 == 256, "the finishing steps use 256 threads");
-    using A = AdjGeo<NB>;
-    constexpr int NT = A::NT, R = 16 * NT;
+    using A = AdjGeo<NB, CPLX>;
+    constexpr int NT = A::NT, NC = A::NC, CH = A::CH, R = 16 * NT;
     constexpr int64_t nt1 = NB / 16;
-    __shared__ double tr[RW][2][16][17];   // per-wave transposes
-    __shared__ double P1[R][17], P2[R][17], Vs[R][17];
-    __shared__ double Ts[16][17], U1[16][17], U2[16][17], Cm[16][17];
-    __shared__ double dts[16], taus[16];
+    // the per-wave transposes of the column loop and the combined sums after
+    // it share one area
+    __shared__ union {
+        double tr[RW][2][NC][16][17];
+        struct {
+            double P1[R][16][NC], P2[R][16][NC];
+        } f;
+    } U;
+    __shared__ double Vs[R][16][NC];
+    __shared__ double Ts[16][17][NC], U1[16][17][NC], U2[16][17][NC], Cm[16][17][NC];
+    __shared__ double dts[16][NC], taus[16][NC];
     __shared__ int64_t s_j, s_t;
+    auto& P1 = U.f.P1;
+    auto& P2 = U.f.P2;
 
     const int tid = threadIdx.x, lane = tid & 63;
     const int w = __builtin_amdgcn_readfirstlane(tid >> 6);
@@ -367,89 +487,145 @@ __global__ __launch_bounds__(64 * RW, 2) void k_adj_reduce(int64_t n, int64_t ns
         s_t = lo * nt1 + (b - slot_base(lo, nblk, nt1));
     }
     const double* pk = apk + (size_t)b * A::APB;
-    double rt[4], st[4];
+    double rt[4][NC], st[4][NC];
 #pragma unroll
-    for (int u = 0; u < 4; ++u) {
-        rt[u] = pk[A::RT_OFF + u * 64 + lane];
-        st[u] = pk[A::ST_OFF + u * 64 + lane];
-    }
-    double (*Ma)[17] = tr[w][0];
-    double (*Mb)[17] = tr[w][1];
-    d4 p1[NT], p2[NT], dg = d4{0.0, 0.0, 0.0, 0.0};
+    for (int u = 0; u < 4; ++u)
 #pragma unroll
-    for (int q = 0; q < NT; ++q) p1[q] = p2[q] = d4{0.0, 0.0, 0.0, 0.0};
+        for (int pl = 0; pl < NC; ++pl) {
+            rt[u][pl] = CPLX ? 0.0 : pk[A::RT_OFF + u * CH + pl * 64 + lane];
+            st[u][pl] = CPLX ? 0.0 : pk[A::ST_OFF + u * CH + pl * 64 + lane];
+        }
+    auto& Ma = U.tr[w][0];
+    auto& Mb = U.tr[w][1];
+    Tile<CPLX> p1[NT], p2[NT], dg = tile_zero<CPLX>();
+#pragma unroll
+    for (int q = 0; q < NT; ++q) p1[q] = p2[q] = tile_zero<CPLX>();
 
+    // Complex: X and Go are not kept in registers between their two uses
+    // (V^H X, V^H Go, then P1 and P2) but read again (from the caches: the
+    // wave has just read them), which leaves the accumulators room without
+    // spilling.
+    constexpr bool KEEPX = !CPLX;
+    auto load_t = [&](const double* __restrict__ src, size_t o, Tile<CPLX>& t) {
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+            t.re[e] = __builtin_nontemporal_load(&src[o + e * 64]);
+            if constexpr (CPLX) t.im[e] = __builtin_nontemporal_load(&src[o + 256 + e * 64]);
+        }
+    };
     for (int64_t s = w; s < nstrips; s += RW) {
-        const size_t off = ((size_t)b * NT * nstrips + s) * 256 + lane;
-        Tile<false> x[NT], go[NT];
+        const size_t off = ((size_t)b * NT * nstrips + s) * 256 * NC + lane;
+        const size_t qstride = (size_t)nstrips * 256 * NC;
+        // complex: the V^H chunks are read again for every strip (from L1/L2)
+        // rather than held in registers across the loop
+        const double* pkv = pk;
+        if constexpr (!KEEPX) asm volatile("" : "+s"(pkv));
+        Tile<CPLX> x[KEEPX ? NT : 1], go[KEEPX ? NT : 1];
 #pragma unroll
-        for (int q = 0; q < NT; ++q)
-#pragma unroll
-            for (int e = 0; e < 4; ++e) {
-                x[q].re[e] = __builtin_nontemporal_load(&ckpt[off + (size_t)q * nstrips * 256 + e * 64]);
-                go[q].re[e] = __builtin_nontemporal_load(&gck[off + (size_t)q * nstrips * 256 + e * 64]);
+        for (int q = 0; q < NT; ++q) {
+            if constexpr (KEEPX) {
+                load_t(ckpt, off + q * qstride, x[q]);
+                load_t(gck, off + q * qstride, go[q]);
             }
-        // Ax = V^T X, Bt = V^T Go (V^T chunks from L1/L2: shared by the waves)
-        d4 ax[2], bt[2];
-        ax[0] = ax[1] = bt[0] = bt[1] = d4{0.0, 0.0, 0.0, 0.0};
+        }
+        // Ax = V^H X, Bt = V^H Go (V^H chunks from L1/L2: shared by the waves)
+        Tile<CPLX> ax[2], bt[2];
+        ax[0] = ax[1] = bt[0] = bt[1] = tile_zero<CPLX>();
 #pragma unroll
         for (int c = 0; c < 4 * NT; ++c) {
             const int q = c >> 2, u = c & 3;
-            const double a = pk[A::VT_OFF + c * 64 + lane];
-            ax[q & 1] = mfma(a, x[q].re[u], ax[q & 1]);
-            bt[q & 1] = mfma(a, go[q].re[u], bt[q & 1]);
+            if (!KEEPX && u == 0) {
+                load_t(ckpt, off + q * qstride, x[0]);
+                load_t(gck, off + q * qstride, go[0]);
+            }
+            const Tile<CPLX>& xq = x[KEEPX ? q : 0];
+            const Tile<CPLX>& gq = go[KEEPX ? q : 0];
+            const double ar = pkv[A::VT_OFF + c * CH + lane];
+            const double ai = CPLX ? pkv[A::VT_OFF + c * CH + 64 + lane] : 0.0;
+            cmma<CPLX>(ar, ai, xq.re[u], tim(xq, u), ax[q & 1]);
+            cmma<CPLX>(ar, ai, gq.re[u], tim(gq, u), bt[q & 1]);
         }
-        const d4 Ax = ax[0] + ax[1], Bt = bt[0] + bt[1];
-        // W^T = R^T Ax, g^T = S^T Bt
-        d4 Wt = d4{0.0, 0.0, 0.0, 0.0}, Gt = Wt;
+        const Tile<CPLX> Ax = tile_add(ax[0], ax[1]), Bt = tile_add(bt[0], bt[1]);
+        // W = R Ax, g = S Bt (reflectors x columns)
+        Tile<CPLX> Wt = tile_zero<CPLX>(), Gt = tile_zero<CPLX>();
 #pragma unroll
         for (int u = 0; u < 4; ++u) {
-            Wt = mfma(rt[u], Ax[u], Wt);
-            Gt = mfma(st[u], Bt[u], Gt);
+            if constexpr (!KEEPX) {
+#pragma unroll
+                for (int pl = 0; pl < NC; ++pl) {
+                    rt[u][pl] = pkv[A::RT_OFF + u * CH + pl * 64 + lane];
+                    st[u][pl] = pkv[A::ST_OFF + u * CH + pl * 64 + lane];
+                }
+            }
+            cmma<CPLX>(rt[u][0], rt[u][NC - 1], Ax.re[u], tim(Ax, u), Wt);
+            cmma<CPLX>(st[u][0], st[u][NC - 1], Bt.re[u], tim(Bt, u), Gt);
         }
-        // chunk u of W^T and g^T (B operands) through an LDS transpose
+        // chunk u of W and g through an LDS transpose: lane (j + 16k) holds
+        // W[j][4u + k], the A operand of chunk u of W and the B operand of
+        // chunk u of W^T (likewise g)
 #pragma unroll
         for (int e = 0; e < 4; ++e) {
-            Ma[rsub + 4 * e][cl] = Wt[e];
-            Mb[rsub + 4 * e][cl] = Gt[e];
+            Ma[0][rsub + 4 * e][cl] = Wt.re[e];
+            Mb[0][rsub + 4 * e][cl] = Gt.re[e];
+            if constexpr (CPLX) {
+                Ma[NC - 1][rsub + 4 * e][cl] = Wt.im[e];
+                Mb[NC - 1][rsub + 4 * e][cl] = Gt.im[e];
+            }
         }
         wave_lds_sync();
-        double bw[4], bg[4];
+        double bw[4][NC], bg[4][NC];
 #pragma unroll
-        for (int u = 0; u < 4; ++u) {
-            bw[u] = Ma[cl][4 * u + rsub];
-            bg[u] = Mb[cl][4 * u + rsub];
-        }
+        for (int u = 0; u < 4; ++u)
+#pragma unroll
+            for (int pl = 0; pl < NC; ++pl) {
+                bw[u][pl] = Ma[pl][cl][4 * u + rsub];
+                bg[u][pl] = Mb[pl][cl][4 * u + rsub];
+            }
         wave_lds_sync();
-        // g W^T: its diagonal is sum_c g_p w_p (bg read as the A operand is
-        // chunk u of g, reflectors x columns)
+        // g conj(W)^T: its diagonal is sum_c g_p conj(w_p)
 #pragma unroll
-        for (int u = 0; u < 4; ++u) dg = mfma(bg[u], bw[u], dg);
-        // P1 += Go W, P2 += X g, tile by tile (Go and X transposed to A operands)
+        for (int u = 0; u < 4; ++u) cmma<CPLX>(bg[u][0], bg[u][NC - 1], bw[u][0], -bw[u][NC - 1], dg);
+        // P1 += Go conj(W)^T, P2 += X conj(g)^T, tile by tile (Go and X
+        // transposed to A operands)
+        if constexpr (!KEEPX) asm volatile("" ::: "memory");   // read again, do not keep
 #pragma unroll
         for (int q = 0; q < NT; ++q) {
+            if (!KEEPX) {
+                load_t(ckpt, off + q * qstride, x[0]);
+                load_t(gck, off + q * qstride, go[0]);
+            }
+            const Tile<CPLX>& xq = x[KEEPX ? q : 0];
+            const Tile<CPLX>& gq = go[KEEPX ? q : 0];
 #pragma unroll
             for (int e = 0; e < 4; ++e) {
-                Ma[rsub + 4 * e][cl] = go[q].re[e];
-                Mb[rsub + 4 * e][cl] = x[q].re[e];
+                Ma[0][rsub + 4 * e][cl] = gq.re[e];
+                Mb[0][rsub + 4 * e][cl] = xq.re[e];
+                if constexpr (CPLX) {
+                    Ma[NC - 1][rsub + 4 * e][cl] = gq.im[e];
+                    Mb[NC - 1][rsub + 4 * e][cl] = xq.im[e];
+                }
             }
             wave_lds_sync();
-            double ag[4], axx[4];
+            double ag[4][NC], axx[4][NC];
 #pragma unroll
-            for (int u = 0; u < 4; ++u) {
-                ag[u] = Ma[cl][4 * u + rsub];
-                axx[u] = Mb[cl][4 * u + rsub];
-            }
+            for (int u = 0; u < 4; ++u)
+#pragma unroll
+                for (int pl = 0; pl < NC; ++pl) {
+                    ag[u][pl] = Ma[pl][cl][4 * u + rsub];
+                    axx[u][pl] = Mb[pl][cl][4 * u + rsub];
+                }
             wave_lds_sync();
 #pragma unroll
             for (int u = 0; u < 4; ++u) {
-                p1[q] = mfma(ag[u], bw[u], p1[q]);
-                p2[q] = mfma(axx[u], bg[u], p2[q]);
+                cmma<CPLX>(ag[u][0], ag[u][NC - 1], bw[u][0], -bw[u][NC - 1], p1[q]);
+                cmma<CPLX>(axx[u][0], axx[u][NC - 1], bg[u][0], -bg[u][NC - 1], p2[q]);
             }
         }
     }
+    __syncthreads();   // every wave is done with its transposes (the sums reuse them)
     // combine the waves in order: P1[16q + rsub + 4e][cl] is element e of
-    // p1[q]; element (p, p) of g W^T sits in lane p + 16 (p % 4), element p / 4
+    // p1[q]; element (p, p) of g conj(W)^T sits in lane p + 16 (p % 4),
+    // element p / 4
     const int de = (cl - rsub) >> 2;
     const bool dlane = ((cl - rsub) & 3) == 0 && cl >= rsub;
     for (int ww = 0; ww < RW; ++ww) {
@@ -459,43 +635,89 @@ __global__ __launch_bounds__(64 * RW, 2) void k_adj_reduce(int64_t n, int64_t ns
 #pragma unroll
                 for (int e = 0; e < 4; ++e) {
                     const int r = 16 * q + rsub + 4 * e;
-                    P1[r][cl] = (ww ? P1[r][cl] : 0.0) + p1[q][e];
-                    P2[r][cl] = (ww ? P2[r][cl] : 0.0) + p2[q][e];
+                    P1[r][cl][0] = (ww ? P1[r][cl][0] : 0.0) + p1[q].re[e];
+                    P2[r][cl][0] = (ww ? P2[r][cl][0] : 0.0) + p2[q].re[e];
+                    if constexpr (CPLX) {
+                        P1[r][cl][NC - 1] = (ww ? P1[r][cl][NC - 1] : 0.0) + p1[q].im[e];
+                        P2[r][cl][NC - 1] = (ww ? P2[r][cl][NC - 1] : 0.0) + p2[q].im[e];
+                    }
                 }
             if (dlane) {
-                const double d = de == 0 ? dg[0] : de == 1 ? dg[1] : de == 2 ? dg[2] : dg[3];
-                dts[cl] = (ww ? dts[cl] : 0.0) - d;
+                const double dr = de == 0 ? dg.re[0] : de == 1 ? dg.re[1] : de == 2 ? dg.re[2] : dg.re[3];
+                dts[cl][0] = (ww ? dts[cl][0] : 0.0) - dr;
+                if constexpr (CPLX) {
+                    const double di = de == 0 ? dg.im[0] : de == 1 ? dg.im[1] : de == 2 ? dg.im[2] : dg.im[3];
+                    dts[cl][NC - 1] = (ww ? dts[cl][NC - 1] : 0.0) - di;
+                }
             }
         }
         __syncthreads();
     }
-    for (int idx = tid; idx < R * 16; idx += 256) {   // V[r][p] from the V^T chunks
+    for (int idx = tid; idx < R * 16; idx += 256) {   // V[r][p] from the V^H chunks
         const int r = idx / 16, p = idx % 16;
         const int c = 4 * (r / 16) + (r % 16) / 4, l = p + 16 * (r % 4);
-        Vs[r][p] = pk[A::VT_OFF + c * 64 + l];
+        Vs[r][p][0] = pk[A::VT_OFF + c * CH + l];
+        if constexpr (CPLX) Vs[r][p][NC - 1] = -pk[A::VT_OFF + c * CH + 64 + l];
     }
-    Ts[tid / 16][tid % 16] = pk[A::T_OFF + tid];
-    if (tid < 16) taus[tid] = pk[A::TAU_OFF + tid];
+#pragma unroll
+    for (int pl = 0; pl < NC; ++pl) Ts[tid / 16][tid % 16][pl] = pk[A::T_OFF + tid * NC + pl];
+    if (tid < 16) {
+#pragma unroll
+        for (int pl = 0; pl < NC; ++pl) taus[tid][pl] = pk[A::TAU_OFF + tid * NC + pl];
+    }
     __syncthreads();
-    {
+    {   // U1 = V^H P1, U2 = V^H P2
         const int a = tid / 16, p = tid % 16;
-        double u1 = 0.0, u2 = 0.0;
+        double u1r = 0.0, u1i = 0.0, u2r = 0.0, u2i = 0.0;
         for (int r = 0; r < R; ++r) {
-            u1 += Vs[r][a] * P1[r][p];
-            u2 += Vs[r][a] * P2[r][p];
+            const double vr = Vs[r][a][0];
+            if constexpr (CPLX) {
+                const double vi = -Vs[r][a][NC - 1];   // conj
+                u1r += vr * P1[r][p][0] - vi * P1[r][p][NC - 1];
+                u1i += vr * P1[r][p][NC - 1] + vi * P1[r][p][0];
+                u2r += vr * P2[r][p][0] - vi * P2[r][p][NC - 1];
+                u2i += vr * P2[r][p][NC - 1] + vi * P2[r][p][0];
+            } else {
+                u1r += vr * P1[r][p][0];
+                u2r += vr * P2[r][p][0];
+            }
         }
-        U1[a][p] = u1;
-        U2[a][p] = u2;
+        U1[a][p][0] = u1r;
+        U2[a][p][0] = u2r;
+        if constexpr (CPLX) {
+            U1[a][p][NC - 1] = u1i;
+            U2[a][p][NC - 1] = u2i;
+        }
     }
     __syncthreads();
-    {
+    {   // Cm[a][p] = sum_{a2 <= a} conj(T[a2][a]) U1[a2][p]   (a < p)
+        //          = sum_{a2 >= a} T[a][a2] U2[a2][p]          (a > p)
         const int a = tid / 16, p = tid % 16;
-        double c = 0.0;
+        double cr = 0.0, ci = 0.0;
         if (a < p)
-            for (int a2 = 0; a2 <= a; ++a2) c += Ts[a2][a] * U1[a2][p];
+            for (int a2 = 0; a2 <= a; ++a2) {
+                const double tr = Ts[a2][a][0];
+                if constexpr (CPLX) {
+                    const double ti = -Ts[a2][a][NC - 1];
+                    cr += tr * U1[a2][p][0] - ti * U1[a2][p][NC - 1];
+                    ci += tr * U1[a2][p][NC - 1] + ti * U1[a2][p][0];
+                } else {
+                    cr += tr * U1[a2][p][0];
+                }
+            }
         if (a > p)
-            for (int a2 = a; a2 < 16; ++a2) c += Ts[a][a2] * U2[a2][p];
-        Cm[a][p] = c;
+            for (int a2 = a; a2 < 16; ++a2) {
+                const double tr = Ts[a][a2][0];
+                if constexpr (CPLX) {
+                    const double ti = Ts[a][a2][NC - 1];
+                    cr += tr * U2[a2][p][0] - ti * U2[a2][p][NC - 1];
+                    ci += tr * U2[a2][p][NC - 1] + ti * U2[a2][p][0];
+                } else {
+                    cr += tr * U2[a2][p][0];
+                }
+            }
+        Cm[a][p][0] = cr;
+        if constexpr (CPLX) Cm[a][p][NC - 1] = ci;
     }
     __syncthreads();
     const int64_t j = s_j, t = s_t;
@@ -507,15 +729,42 @@ __global__ __launch_bounds__(64 * RW, 2) void k_adj_reduce(int64_t n, int64_t ns
         const int64_t k = stage_offset(n, NB, s) + j;
         const int64_t r0 = s + 1 + j * NB;
         const int len = (int)(n - r0 < NB ? n - r0 : NB);
-        double val = 0.0;
+        double vr = 0.0, vi = 0.0;
         if (i < len) {
             const int r = p + 1 + i;
-            double term = P1[r][p] + P2[r][p];
-            for (int a = 0; a < 16; ++a) term -= Vs[r][a] * Cm[a][p];
-            val = -taus[p] * term;
+            // t1 = P1 - V_<p Cm_<p, t2 = P2 - V_>p Cm_>p on row r
+            double t1r = P1[r][p][0], t1i = CPLX ? P1[r][p][NC - 1] : 0.0;
+            double t2r = P2[r][p][0], t2i = CPLX ? P2[r][p][NC - 1] : 0.0;
+            for (int a = 0; a < 16; ++a) {
+                if (a == p) continue;
+                const double xr = Vs[r][a][0], cr = Cm[a][p][0];
+                double pr, pi = 0.0;
+                if constexpr (CPLX) {
+                    const double xi = Vs[r][a][NC - 1], ci = Cm[a][p][NC - 1];
+                    pr = xr * cr - xi * ci;
+                    pi = xr * ci + xi * cr;
+                } else {
+                    pr = xr * cr;
+                }
+                if (a < p) {
+                    t1r -= pr;
+                    t1i -= pi;
+                } else {
+                    t2r -= pr;
+                    t2i -= pi;
+                }
+            }
+            const double ur = taus[p][0], ui = CPLX ? taus[p][NC - 1] : 0.0;
+            // -(conj(tau) t1 + tau t2)
+            vr = -((ur * t1r + ui * t1i) + (ur * t2r - ui * t2i));
+            vi = -((ur * t1i - ui * t1r) + (ur * t2i + ui * t2r));
         }
-        dv[k * NB + i] = val;
-        if (i == 0) dtau[k] = dts[p];
+        dv[(k * NB + i) * NC] = vr;
+        if constexpr (CPLX) dv[(k * NB + i) * NC + 1] = vi;
+        if (i == 0) {
+#pragma unroll
+            for (int pl = 0; pl < NC; ++pl) dtau[k * NC + pl] = dts[p][pl];
+        }
     }
 }
 
@@ -702,7 +951,8 @@ __global__ void k_fill_zero(double* p, int64_t count)
 // --------------------------------------------------------------------------
 // Host side
 // --------------------------------------------------------------------------
-constexpr int ADJ_WAVES = 8;
+constexpr int ADJ_WAVES = 8;     // waves (slots in flight) per strip, real
+constexpr int ADJ_WAVES_Z = 4;   // the same, complex (registers: one wave per SIMD)
 
 struct AdjLayout {
     size_t zs = 0, fwd = 0, apk = 0, ckpt = 0, gck = 0, part = 0, tape = 0, total = 0;
@@ -713,35 +963,39 @@ size_t al(size_t x) { return (x + 255) / 256 * 256; }
 
 int adj_tiles(int nbw) { return nbw / 16 + 1; }
 
-int adj_apb(int nbw)
+int adj_apb(int nbw, bool cplx)
 {
     switch (nbw) {
-        case 16: return AdjGeo<16>::APB;
-        case 32: return AdjGeo<32>::APB;
-        case 48: return AdjGeo<48>::APB;
-        default: return AdjGeo<64>::APB;
+        case 16: return cplx ? AdjGeo<16, true>::APB : AdjGeo<16>::APB;
+        case 32: return cplx ? AdjGeo<32, true>::APB : AdjGeo<32>::APB;
+        case 48: return cplx ? AdjGeo<48, true>::APB : AdjGeo<48>::APB;
+        default: return cplx ? AdjGeo<64, true>::APB : AdjGeo<64>::APB;
     }
 }
 
-AdjLayout adj_layout(int64_t n, int nbw, int64_t nev)
+// Workspace of the adjoint: the blocked layout when use_blocked(n, nbw,
+// cplx) (complex: only that one; the complex streaming form has its own),
+// else the real streaming layout.
+AdjLayout adj_layout(int64_t n, int nbw, int64_t nev, bool cplx = false)
 {
     AdjLayout L;
+    const size_t elt = cplx ? 2 * sizeof(double) : sizeof(double);
     size_t off = HDR_BYTES;
     L.zs = off;
-    off = al(off + (size_t)n * nev * sizeof(double));
-    if (use_blocked(n, nbw, false)) {
+    off = al(off + (size_t)n * nev * elt);
+    if (use_blocked(n, nbw, cplx)) {
         const int nt = adj_tiles(nbw);
         L.nblocks = blocked_num_blocks(n, nbw);
         L.nstrips = (nev + 15) / 16;
-        const size_t pb = (size_t)packed_block_doubles(nbw, false);
+        const size_t pb = (size_t)packed_block_doubles(nbw, cplx);
         L.fwd = off;
         off = al(off + (size_t)L.nblocks * pb * sizeof(double));
         L.apk = off;
-        off = al(off + (size_t)L.nblocks * adj_apb(nbw) * sizeof(double));
+        off = al(off + (size_t)L.nblocks * adj_apb(nbw, cplx) * sizeof(double));
         L.ckpt = off;
-        off = al(off + (size_t)L.nblocks * nt * L.nstrips * 256 * sizeof(double));
+        off = al(off + (size_t)L.nblocks * nt * L.nstrips * 256 * elt);
         L.gck = off;   // every block's output-gradient window, checkpoint layout
-        off = al(off + (size_t)L.nblocks * nt * L.nstrips * 256 * sizeof(double));
+        off = al(off + (size_t)L.nblocks * nt * L.nstrips * 256 * elt);
     } else {
         const int64_t nblk = (n - 2 + KB - 1) / KB;
         int64_t ckrows = 0, taperows = 0;
@@ -798,8 +1052,9 @@ void blocked_forward(int64_t n, int64_t nev, const double* hv, const double* ht,
     double* fwd = (double*)(ws + L.fwd);
     const unsigned nb = (unsigned)L.nblocks, ns = (unsigned)L.nstrips;
     hipLaunchKernelGGL((k_pack<NB, false>), dim3(nb), dim3(256), 0, st, n, hv, ht, fwd);
-    hipLaunchKernelGGL((k_blocked_ckpt<NB, ADJ_WAVES>), dim3(ns), dim3(64 * ADJ_WAVES), 0, st, n,
-                       nev, (const double*)fwd, Z, ldz, (double*)(ws + L.ckpt), (unsigned*)ws);
+    hipLaunchKernelGGL((k_blocked_ckpt<NB, ADJ_WAVES, false>), dim3(ns), dim3(64 * ADJ_WAVES), 0,
+                       st, n, nev, (const double*)fwd, Z, ldz, (double*)(ws + L.ckpt),
+                       (unsigned*)ws);
 }
 
 template <int NB>
@@ -810,31 +1065,33 @@ void blocked_backward(int64_t n, int64_t nev, const double* hv, const double* ht
     double* apk = (double*)(ws + L.apk);
     double* gck = (double*)(ws + L.gck);
     const unsigned nb = (unsigned)L.nblocks, ns = (unsigned)L.nstrips;
-    hipLaunchKernelGGL((k_pack_adj<NB>), dim3(nb), dim3(256), 0, st, n, hv, ht, apk);
-    hipLaunchKernelGGL((k_adj_sweep<NB, ADJ_WAVES>), dim3(ns), dim3(64 * ADJ_WAVES), 0, st, n,
-                       nev, (const double*)apk, G, ldg, gck, (unsigned*)ws);
-    hipLaunchKernelGGL((k_adj_reduce<NB, 4>), dim3(nb), dim3(256), 0, st, n, (int64_t)ns,
+    hipLaunchKernelGGL((k_pack_adj<NB, false>), dim3(nb), dim3(256), 0, st, n, hv, ht, apk);
+    hipLaunchKernelGGL((k_adj_sweep<NB, ADJ_WAVES, false>), dim3(ns), dim3(64 * ADJ_WAVES), 0, st,
+                       n, nev, (const double*)apk, G, ldg, gck, (unsigned*)ws);
+    hipLaunchKernelGGL((k_adj_reduce<NB, 4, false>), dim3(nb), dim3(256), 0, st, n, (int64_t)ns,
                        (const double*)apk, (const double*)(ws + L.ckpt), (const double*)gck, dv,
                        dtau);
 }
 
 // Both halves in one go (the one-call adjoint): the checkpointing forward and
-// the backward sweep share one launch, then the reduction.
-template <int NB>
+// the backward sweep share one launch, then the reduction.  Real or complex
+// (interleaved re, im) data.
+template <int NB, bool CPLX>
 void blocked_both(int64_t n, int64_t nev, const double* hv, const double* ht, double* Z,
                   int64_t ldz, double* G, int64_t ldg, double* dv, double* dtau, char* ws,
                   const AdjLayout& L, hipStream_t st)
 {
+    constexpr int NW = CPLX ? ADJ_WAVES_Z : ADJ_WAVES;
     double* fwd = (double*)(ws + L.fwd);
     double* apk = (double*)(ws + L.apk);
     double* gck = (double*)(ws + L.gck);
     const unsigned nb = (unsigned)L.nblocks, ns = (unsigned)L.nstrips;
-    hipLaunchKernelGGL((k_pack<NB, false>), dim3(nb), dim3(256), 0, st, n, hv, ht, fwd);
-    hipLaunchKernelGGL((k_pack_adj<NB>), dim3(nb), dim3(256), 0, st, n, hv, ht, apk);
-    hipLaunchKernelGGL((k_adj_fwd_sweep<NB, ADJ_WAVES>), dim3(2 * ns), dim3(64 * ADJ_WAVES), 0,
-                       st, n, nev, (const double*)fwd, Z, ldz, (double*)(ws + L.ckpt),
+    hipLaunchKernelGGL((k_pack<NB, CPLX>), dim3(nb), dim3(256), 0, st, n, hv, ht, fwd);
+    hipLaunchKernelGGL((k_pack_adj<NB, CPLX>), dim3(nb), dim3(256), 0, st, n, hv, ht, apk);
+    hipLaunchKernelGGL((k_adj_fwd_sweep<NB, NW, CPLX>), dim3(2 * ns), dim3(64 * NW), 0, st, n,
+                       nev, (const double*)fwd, Z, ldz, (double*)(ws + L.ckpt),
                        (const double*)apk, G, ldg, gck, (unsigned*)ws);
-    hipLaunchKernelGGL((k_adj_reduce<NB, 4>), dim3(nb), dim3(256), 0, st, n, (int64_t)ns,
+    hipLaunchKernelGGL((k_adj_reduce<NB, 4, CPLX>), dim3(nb), dim3(256), 0, st, n, (int64_t)ns,
                        (const double*)apk, (const double*)(ws + L.ckpt), (const double*)gck, dv,
                        dtau);
 }
@@ -892,6 +1149,38 @@ int zero_grads(int64_t K, int nbw, double* dv, double* dtau, hipStream_t st)
 
 }  // namespace
 
+// Blocked complex adjoint, called by trans_ev_tridi_to_band_adjoint_z (in
+// trbt_adjoint_z.hip) after its argument checks when use_blocked(n, nbw,
+// true); K > 0 and nev > 0.  Not exported.
+__attribute__((visibility("hidden"))) size_t trbt_adjoint_blocked_bytes_z(int64_t n, int nbw,
+                                                                          int64_t nev)
+{
+    return adj_layout(n, nbw, nev, true).total;
+}
+
+__attribute__((visibility("hidden"))) int trbt_adjoint_blocked_z(
+    int64_t n, int nbw, int64_t nev, const double* hv, const double* ht, const double* Z_in,
+    int64_t ldz, double* G, int64_t ldg, double* dv, double* dtau, void* work,
+    size_t work_bytes, hipStream_t st)
+{
+    const AdjLayout L = adj_layout(n, nbw, nev, true);
+    if (!work || work_bytes < L.total) return TRBT_ERR_WORKSPACE;
+    char* ws = (char*)work;
+    hipLaunchKernelGGL(k_zero_words, dim3(1), dim3(64), 0, st, (unsigned*)work, 64);
+    double* Zs = (double*)(ws + L.zs);
+    if (hipMemcpy2DAsync(Zs, (size_t)n * 16, Z_in, (size_t)ldz * 16, (size_t)n * 16,
+                         (size_t)nev, hipMemcpyDeviceToDevice, st) != hipSuccess)
+        return TRBT_ERR_HIP;
+    switch (nbw) {
+        case 16: blocked_both<16, true>(n, nev, hv, ht, Zs, n, G, ldg, dv, dtau, ws, L, st); break;
+        case 32: blocked_both<32, true>(n, nev, hv, ht, Zs, n, G, ldg, dv, dtau, ws, L, st); break;
+        case 48: blocked_both<48, true>(n, nev, hv, ht, Zs, n, G, ldg, dv, dtau, ws, L, st); break;
+        case 64: blocked_both<64, true>(n, nev, hv, ht, Zs, n, G, ldg, dv, dtau, ws, L, st); break;
+        default: return TRBT_ERR_INTERNAL;
+    }
+    return hipGetLastError() == hipSuccess ? TRBT_SUCCESS : TRBT_ERR_HIP;
+}
+
 extern "C" {
 
 int trbt_adjoint_workspace_bytes_d(int64_t n, int nbw, int64_t nev, int ckpt_every,
@@ -932,10 +1221,10 @@ int trans_ev_tridi_to_band_adjoint_d(int64_t n, int nbw, int64_t nev, const doub
         return TRBT_ERR_HIP;
     if (use_blocked(n, nbw, false)) {
         switch (nbw) {
-            case 16: blocked_both<16>(n, nev, hh_v, hh_tau, Zs, n, G, ldg, dv, dtau, ws, L, st); break;
-            case 32: blocked_both<32>(n, nev, hh_v, hh_tau, Zs, n, G, ldg, dv, dtau, ws, L, st); break;
-            case 48: blocked_both<48>(n, nev, hh_v, hh_tau, Zs, n, G, ldg, dv, dtau, ws, L, st); break;
-            case 64: blocked_both<64>(n, nev, hh_v, hh_tau, Zs, n, G, ldg, dv, dtau, ws, L, st); break;
+            case 16: blocked_both<16, false>(n, nev, hh_v, hh_tau, Zs, n, G, ldg, dv, dtau, ws, L, st); break;
+            case 32: blocked_both<32, false>(n, nev, hh_v, hh_tau, Zs, n, G, ldg, dv, dtau, ws, L, st); break;
+            case 48: blocked_both<48, false>(n, nev, hh_v, hh_tau, Zs, n, G, ldg, dv, dtau, ws, L, st); break;
+            case 64: blocked_both<64, false>(n, nev, hh_v, hh_tau, Zs, n, G, ldg, dv, dtau, ws, L, st); break;
             default: return TRBT_ERR_INTERNAL;
         }
         return hipGetLastError() == hipSuccess ? TRBT_SUCCESS : TRBT_ERR_HIP;

@@ -341,6 +341,13 @@ ZLayout zlayout(int64_t n, int nbw, int64_t nev)
 
 }  // namespace
 
+// The blocked (compact-WY, FP64 MFMA) complex adjoint of trbt_adjoint.hip,
+// taken for nbw in {16, 32, 48, 64}.
+size_t trbt_adjoint_blocked_bytes_z(int64_t n, int nbw, int64_t nev);
+int trbt_adjoint_blocked_z(int64_t n, int nbw, int64_t nev, const double* hv, const double* ht,
+                           const double* Z_in, int64_t ldz, double* G, int64_t ldg, double* dv,
+                           double* dtau, void* work, size_t work_bytes, hipStream_t st);
+
 extern "C" {
 
 int trbt_adjoint_workspace_bytes_z(int64_t n, int nbw, int64_t nev, int ckpt_every,
@@ -351,7 +358,12 @@ int trbt_adjoint_workspace_bytes_z(int64_t n, int nbw, int64_t nev, int ckpt_eve
     if (nev < 0 || nev > n) return -3;
     if (ckpt_every != 0 && ckpt_every != 16) return -4;
     if (!bytes) return -5;
-    *bytes = (num_reflectors(n, nbw) > 0 && nev > 0) ? zlayout(n, nbw, nev).total : 0;
+    if (num_reflectors(n, nbw) == 0 || nev == 0)
+        *bytes = 0;
+    else if (use_blocked(n, nbw, true))
+        *bytes = trbt_adjoint_blocked_bytes_z(n, nbw, nev);
+    else
+        *bytes = zlayout(n, nbw, nev).total;
     return TRBT_SUCCESS;
 }
 
@@ -391,6 +403,10 @@ int trans_ev_tridi_to_band_adjoint_z(int64_t n, int nbw, int64_t nev, const trbt
                            2 * K);
         return hipGetLastError() == hipSuccess ? TRBT_SUCCESS : TRBT_ERR_HIP;
     }
+    if (use_blocked(n, nbw, true))
+        return trbt_adjoint_blocked_z(n, nbw, nev, (const double*)hh_v, (const double*)hh_tau,
+                                      (const double*)Z_in, ldz, (double*)G, ldg, dvp, dtp, work,
+                                      work_bytes, st);
     const ZLayout L = zlayout(n, nbw, nev);
     if (!work || work_bytes < L.total) return TRBT_ERR_WORKSPACE;
     char* ws = (char*)work;

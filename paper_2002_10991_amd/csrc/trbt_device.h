@@ -17,7 +17,8 @@
 //    by a dot product and an axpy on the column in global memory, in a
 //    blocked topological order of the reflector DAG.  Any nbw.
 //
-//  * blocked ("tile ring", nbw a multiple of 16, up to 64): the reflectors
+//  * blocked ("tile ring", nbw a multiple of 16, up to 64 in every form
+//    and up to 128 for the single-problem forward): the reflectors
 //    of one slot over 16 consecutive stages are merged into one compact-WY
 //    factor  H_a ... H_b = I - V T V^H  (Schreiber & Van Loan); a pack
 //    kernel precomputes, per (slot, 16-stage block), A1 = T V^H and -V in
@@ -706,8 +707,9 @@ __device__ inline void lds_get(Tile<CPLX> (&t)[CT], const double* __restrict__ s
 // also written to ckpt (non-temporal stores: read once, much later, so they
 // should not displace the operand stream in the caches), one 16x16 tile at a
 // time in register order:
-//   ckpt[(((b * NT + q) * nstrips + strip) * 4 + e) * 64 + lane]
-// b = the block's slot-major index, q = tile of the window, e = element.
+//   ckpt[((((b * NT + q) * nstrips + strip) * NC + plane) * 4 + e) * 64 + lane]
+// b = the block's slot-major index, q = tile of the window, plane = real or
+// imaginary part (NC = 2 complex, 1 real), e = element.
 template <int NB, int CT, bool CPLX, int D, int NW, bool CKPT = false>
 __device__ __attribute__((always_inline)) inline void blocked_strip(int64_t n, int64_t nev, const double* __restrict__ wsb,
                                      double* __restrict__ Z, int64_t ldz,
@@ -720,7 +722,7 @@ __device__ __attribute__((always_inline)) inline void blocked_strip(int64_t n, i
     int xput = 0, xget = 0;   // exchange tiles this wave has put / taken so far
     // last values read from the counters this wave waits on (all only grow)
     int seen_prog = 0, seen_written = 0, seen_consumed = 0;
-    static_assert(!CKPT || (CT == 1 && !CPLX), "checkpoints: real, one 16-column tile");
+    static_assert(!CKPT || CT == 1, "checkpoints: one 16-column tile");
     using G = Geo<NB, CPLX>;
     constexpr int NT = G::NT;
     constexpr int NCH = 8 * NT;            // operand chunks per block
@@ -850,6 +852,24 @@ __device__ __attribute__((always_inline)) inline void blocked_strip(int64_t n, i
                         ya[cc] = mfma_n<0>(ar, zr, ya[cc]);
                         yb[cc] = mfma_n<0>(ai, zi, yb[cc]);
                         yc[cc] = mfma_n<0>(as, zr + zi, yc[cc]);
+                    }
+                }
+                if constexpr (CKPT) {
+                    // the block's input window: GEMM1 has only read it and
+                    // GEMM2 is about to overwrite it; window tile q sits in
+                    // register tile (q + rot) mod NT
+                    double* cp = ckpt + ((size_t)(slot_base(j, nblk, nt1) + t - t0) * NT *
+                                             nstrips + strip) * 512 + lane;
+#pragma unroll
+                    for (int h = 0; h < NT; ++h) {
+                        const int q = h >= rot ? h - rot : h + NT - rot;
+#pragma unroll
+                        for (int e = 0; e < 4; ++e) {
+                            __builtin_nontemporal_store(
+                                zt[h][0].re[e], &cp[(size_t)q * nstrips * 512 + e * 64]);
+                            __builtin_nontemporal_store(
+                                zt[h][0].im[e], &cp[(size_t)q * nstrips * 512 + 256 + e * 64]);
+                        }
                     }
                 }
                 // GEMM2 in the other three-product form, which accumulates in
@@ -1020,7 +1040,13 @@ inline int check_device()
     return ok ? TRBT_SUCCESS : TRBT_ERR_DEVICE;
 }
 
+// Band widths with blocked kernels in every form (single problem, batched,
+// adjoint).
 inline bool blocked_eligible(int nbw) { return nbw == 16 || nbw == 32 || nbw == 48 || nbw == 64; }
+
+// Band widths with a blocked single-problem forward kernel: every multiple
+// of 16 up to 128.
+inline bool apply_eligible(int nbw) { return nbw % 16 == 0 && nbw >= 16 && nbw <= 128; }
 
 // Doubles per packed block: the pack kernel's layout, Geo<NB, CPLX>::PB, is
 // the only definition (workspace sizes and stream limits derive from it).
@@ -1031,6 +1057,10 @@ inline int64_t packed_block_doubles(int nbw, bool cplx)
         case 32: return cplx ? Geo<32, true>::PB : Geo<32, false>::PB;
         case 48: return cplx ? Geo<48, true>::PB : Geo<48, false>::PB;
         case 64: return cplx ? Geo<64, true>::PB : Geo<64, false>::PB;
+        case 80: return cplx ? Geo<80, true>::PB : Geo<80, false>::PB;
+        case 96: return cplx ? Geo<96, true>::PB : Geo<96, false>::PB;
+        case 112: return cplx ? Geo<112, true>::PB : Geo<112, false>::PB;
+        case 128: return cplx ? Geo<128, true>::PB : Geo<128, false>::PB;
         default: return 0;
     }
 }
@@ -1048,6 +1078,12 @@ inline bool blocked_fits(int64_t n, int nbw, bool cplx)
 inline bool use_blocked(int64_t n, int nbw, bool cplx)
 {
     return blocked_eligible(nbw) && blocked_fits(n, nbw, cplx);
+}
+
+// The same for the single-problem forward transformation.
+inline bool use_blocked_apply(int64_t n, int nbw, bool cplx)
+{
+    return apply_eligible(nbw) && blocked_fits(n, nbw, cplx);
 }
 
 inline size_t blocked_bytes(int64_t n, int nbw, bool cplx)

@@ -49,8 +49,11 @@ def gpu_adjoint_z(Z, G, V, tau, nbw):
     return g.cpu().numpy(), dv.cpu().numpy(), dt.cpu().numpy()
 
 
+# nbw in {16, 32, 48, 64}: the blocked (compact-WY, MFMA) form; the others:
+# the stage-parallel streaming form
 SHAPES = [(40, 16, 17), (100, 16, 33), (150, 32, 65), (300, 64, 64), (301, 64, 63),
-          (61, 3, 20), (90, 8, 31), (129, 31, 64), (100, 128, 10), (70, 2, 5)]
+          (200, 48, 40), (530, 64, 47), (61, 3, 20), (90, 8, 31), (129, 31, 64), (100, 128, 10),
+          (70, 2, 5)]
 
 
 @pytest.mark.parametrize("n,nbw,nev", SHAPES)

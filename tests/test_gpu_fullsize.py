@@ -52,11 +52,14 @@ def _sampled_check(oracle_mod, Zbuf, Z, V, tau, nbw, cols):
 
 
 @pytest.mark.timeout(900)
-@pytest.mark.parametrize("cfg", ["C2", "C3"])
+@pytest.mark.parametrize("cfg", ["C2", "C3", "C3w"])
 def test_full_size_sampled_columns(oracle_mod, cfg):
+    """C2 and C3 as the benchmark runs them, and C3w: the complex headline
+    size with the widest band the blocked kernel takes (nbw = 128)."""
     import synth
     c = dict(C2=dict(n=8192, nbw=64, nev=4096, dtype="d", seed=1002),
-             C3=dict(n=32768, nbw=64, nev=8192, dtype="z", seed=1003))[cfg]
+             C3=dict(n=32768, nbw=64, nev=8192, dtype="z", seed=1003),
+             C3w=dict(n=32768, nbw=128, nev=8192, dtype="z", seed=1013))[cfg]
     n, nbw, nev, dt = c["n"], c["nbw"], c["nev"], c["dtype"]
     lengths = synth.reflector_lengths(n, nbw)
     V, tau = synth.unitary_reflectors(lengths, nbw, c["seed"], dt)

@@ -2,8 +2,8 @@
 
 The debug build libtrbt_jitter.so (TRBT_WAIT_JITTER) puts a pseudo-random
 delay in front of every wait on an LDS progress / ring counter, so the slot
-hand-offs of the forward, batched and adjoint kernels run in orders the
-release timing never produces.  In a child process on that build:
+hand-offs of the forward, batched and adjoint kernels (real and complex) run
+in orders the release timing never produces.  In a child process on that build:
 * the blocked parity, batched and split-adjoint tests (against the oracle,
   and batched against looped calls bitwise);
 * a digest of the outputs of a few blocked cases, which must equal the
@@ -65,7 +65,8 @@ def test_blocked_tests_pass_under_wait_jitter():
                 "tests/test_gpu_batched.py::test_batched_mixed_two_replays",
                 "tests/test_gpu_batched.py::test_batched_equals_looped_bitwise",
                 "tests/test_gpu_adjoint.py::test_adjoint_vs_oracle",
-                "tests/test_gpu_adjoint.py::test_split_adjoint"], lib)
+                "tests/test_gpu_adjoint.py::test_split_adjoint",
+                "tests/test_gpu_adjoint_z.py::test_complex_adjoint_vs_oracle"], lib)
     assert r.returncode == 0, r.stdout[-4000:] + r.stderr[-4000:]
 
 

@@ -69,10 +69,12 @@ def _relerr(a, b):
 
 
 SHAPES = [
-    # (n, nbw, nev): blocked path (nbw % 16 == 0) and unblocked path
+    # (n, nbw, nev): blocked path (nbw a multiple of 16 up to 128; above 64
+    # with 4 waves per strip) and unblocked path
     (40, 16, 17), (100, 16, 33), (150, 32, 65), (200, 48, 16), (300, 64, 64),
-    (301, 64, 63), (517, 64, 100), (130, 32, 1),
-    (50, 2, 7), (61, 3, 20), (90, 8, 31), (129, 31, 64), (140, 33, 65), (100, 128, 10),
+    (301, 64, 63), (517, 64, 100), (130, 32, 1), (100, 128, 10),
+    (400, 80, 50), (500, 96, 70), (700, 112, 33), (1000, 128, 100), (1301, 128, 17),
+    (50, 2, 7), (61, 3, 20), (90, 8, 31), (129, 31, 64), (140, 33, 65), (300, 100, 20),
 ]
 
 
@@ -181,10 +183,11 @@ def _rescaled_nan_tail(V, tau, lengths, dtype, seed):
 
 @pytest.mark.parametrize("dtype", ["d", "z"])
 @pytest.mark.parametrize("n,nbw,nev", [(300, 64, 40), (200, 32, 33), (150, 16, 20),
-                                       (150, 24, 20), (97, 7, 10), (100, 128, 9)])
+                                       (150, 24, 20), (97, 7, 10), (100, 128, 9),
+                                       (600, 96, 20), (300, 100, 9)])
 def test_parity_v0_not_one_nan_tail(oracle_mod, dtype, n, nbw, nev):
     """v[0] != 1 and NaN beyond each reflector's length, on the blocked
-    (nbw in {16, 32, 64}) and the streaming path (24, 7, 128)."""
+    (nbw in {16, 32, 64, 96, 128}) and the streaming path (24, 7, 100)."""
     Z, V, tau = _inputs(n, nbw, nev, dtype, 3000 + n + nbw, oracle_mod)
     lengths = oracle_mod.reflector_table(n, nbw)[3]
     V2, t2, Vz = _rescaled_nan_tail(V, tau, lengths, dtype, 5 + n)
