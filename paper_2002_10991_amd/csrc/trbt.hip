@@ -16,6 +16,77 @@ namespace {
 // --------------------------------------------------------------------------
 // Host side
 // --------------------------------------------------------------------------
+
+// Slot groups: when a problem has fewer column strips than the device has
+// CUs, G workgroups share each strip (at most GMAX), with G progress
+// counters per strip in the workspace after the packed blocks (room for
+// 16-column strips, the narrowest, plus 8 strips of padding).
+constexpr int GMAX = 8;
+
+inline size_t group_counter_bytes(int64_t nev)
+{
+    return ((size_t)((nev + 15) / 16 + 8) * GMAX * sizeof(int) + 255) / 256 * 256;
+}
+
+// Workspace of the single-problem forward: packed blocks + group counters.
+inline size_t apply_bytes(int64_t n, int nbw, int64_t nev, bool cplx)
+{
+    return blocked_bytes(n, nbw, cplx) + group_counter_bytes(nev);
+}
+
+// CUs of the current device (looked up once per device id).
+inline int device_cus()
+{
+    static int cached[64];
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return 0;
+    if (dev >= 0 && dev < 64 && cached[dev]) return cached[dev];
+    int cus = 0;
+    if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
+        return 0;
+    if (dev >= 0 && dev < 64) cached[dev] = cus;
+    return cus;
+}
+
+// Launch the blocked forward kernel, with slot groups when the strips alone
+// leave CUs idle and the grid fits on the device at once (a cooperative
+// launch guarantees the workgroups of a strip run concurrently); otherwise
+// one workgroup per strip.
+template <int NB, int CT, bool CPLX, int D, int NW>
+int launch_blocked(int64_t n, int64_t nev, const double* ws, double* Z, int64_t ldz,
+                   unsigned* err, int* gprog, hipStream_t st)
+{
+    const int64_t strips = (nev + 16 * CT - 1) / (16 * CT);
+    const int64_t rounds = (sweeps_in_stage(n, NB, 0) + NW - 1) / NW;
+    const int cus = device_cus();
+    int64_t G = 1;
+    if (cus > 0 && strips < cus) {
+        G = cus / strips;
+        if (G > rounds) G = rounds;
+        if (G > GMAX) G = GMAX;
+    }
+    auto kern = k_blocked<NB, CT, CPLX, D, NW>;
+    if (G > 1) {
+        const int64_t grid = (strips + 7) / 8 * 8 * G;
+        int per_cu = 0;
+        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kern, 64 * NW, 0) ==
+                hipSuccess &&
+            (int64_t)per_cu * cus >= grid) {
+            const int cnt = (int)(strips * G);
+            hipLaunchKernelGGL(k_zero_words, dim3((unsigned)((cnt + 255) / 256)), dim3(256), 0, st,
+                               (unsigned*)gprog, cnt);
+            int g32 = (int)G;
+            void* args[] = {&n, &nev, &ws, &Z, &ldz, &err, &g32, &gprog};
+            if (hipLaunchCooperativeKernel(reinterpret_cast<const void*>(kern), dim3((unsigned)grid),
+                                           dim3(64 * NW), args, 0, st) == hipSuccess)
+                return TRBT_SUCCESS;
+        }
+        (void)hipGetLastError();   // fall back to one workgroup per strip
+    }
+    hipLaunchKernelGGL(kern, dim3((unsigned)strips), dim3(64 * NW), 0, st, n, nev, ws, Z, ldz,
+                       err, 1, (int*)nullptr);
+    return hipGetLastError() == hipSuccess ? TRBT_SUCCESS : TRBT_ERR_HIP;
+}
 template <bool CPLX>
 int prepare(int64_t n, int nbw, const double* hv, const double* ht, void* work,
             size_t work_bytes, void* stream_v)
@@ -67,29 +138,27 @@ int apply(int64_t n, int nbw, int64_t nev, const double* hv, const double* ht, d
     hipStream_t st = (hipStream_t)stream_v;
 
     if (use_blocked_apply(n, nbw, CPLX)) {
-        if (work_bytes < blocked_bytes(n, nbw, CPLX) || !work) return TRBT_ERR_WORKSPACE;
+        if (work_bytes < apply_bytes(n, nbw, nev, CPLX) || !work) return TRBT_ERR_WORKSPACE;
         const double* ws = (const double*)work;
-        const int CT = 1;
-        const int64_t strips = (nev + 16 * CT - 1) / (16 * CT);
+        unsigned* err = (unsigned*)work;
+        int* gprog = (int*)((char*)work + blocked_bytes(n, nbw, CPLX));
         // nbw > 64: windows of 6..9 tiles need one wave per SIMD (4 waves,
         // all 512 registers) and a half-block operand ring
 #define TRBT_MAIN(NBV)                                                                         \
     case NBV: {                                                                                \
         constexpr int NW = NBV <= 64 ? WAVES : 4;                                              \
         constexpr int D = (NBV <= 64 || CPLX) ? ring_depth<NBV, CPLX>() : 4 * (NBV / 16 + 1);  \
-        hipLaunchKernelGGL((k_blocked<NBV, 1, CPLX, D, NW>), dim3((unsigned)strips),           \
-                           dim3(64 * NW), 0, st, n, nev, ws, Z, ldz, (unsigned*)work);         \
-        break;                                                                                 \
+        return launch_blocked<NBV, 1, CPLX, D, NW>(n, nev, ws, Z, ldz, err, gprog, st);        \
     }
         switch (nbw) {
             TRBT_MAIN(16)
             TRBT_MAIN(32)
             TRBT_MAIN(48)
             TRBT_MAIN(64)
-        TRBT_MAIN(80)
-        TRBT_MAIN(96)
-        TRBT_MAIN(112)
-        TRBT_MAIN(128)
+            TRBT_MAIN(80)
+            TRBT_MAIN(96)
+            TRBT_MAIN(112)
+            TRBT_MAIN(128)
             default: return TRBT_ERR_INTERNAL;
         }
 #undef TRBT_MAIN
@@ -150,7 +219,7 @@ int trbt_workspace_bytes(int64_t n, int nbw, int64_t nev, int is_complex, size_t
     if (nev < 0 || nev > n) return -3;
     if (!bytes) return -4;
     *bytes = (use_blocked_apply(n, nbw, is_complex != 0) && num_reflectors(n, nbw) > 0 && nev > 0)
-                 ? blocked_bytes(n, nbw, is_complex != 0)
+                 ? apply_bytes(n, nbw, nev, is_complex != 0)
                  : 0;
     return TRBT_SUCCESS;
 }

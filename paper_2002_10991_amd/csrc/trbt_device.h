@@ -588,6 +588,27 @@ __device__ inline bool wait_counter(int* ctr, int idx, int need, unsigned* err, 
     return true;
 }
 
+// The same wait on a progress counter in global memory, published by a wave
+// of another workgroup with an agent-scope release; the acquire that ends
+// the wait makes that workgroup's earlier stores to Z visible here.
+__device__ inline bool wait_global(const int* ctr, int need, unsigned* err, int lane, int& seen)
+{
+    wait_jitter(need, need);
+    if (seen >= need) return true;
+    unsigned spins = 0;
+    int v;
+    while ((v = __hip_atomic_load(ctr, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) < need) {
+        __builtin_amdgcn_s_sleep(2);
+        if (++spins > (1u << 26)) {
+            if (lane == 0) atomicOr(err, 1u);
+            return false;
+        }
+    }
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+    seen = v;
+    return true;
+}
+
 // Operand ring depth (chunks loaded ahead of use).  The ring position of a
 // chunk is its index in the block's stream modulo D, and the ring runs on
 // into the next block, so D must divide the chunk count per block.  Real
@@ -703,6 +724,15 @@ __device__ inline void lds_get(Tile<CPLX> (&t)[CT], const double* __restrict__ s
 // on entry.  On the (never expected) time-out of a progress wait a wave sets
 // *err and leaves.
 //
+// Slot groups: with ngroups = G > 1 the strip's slots are shared by G
+// workgroups (group grp = 0 .. G-1) that run as one pipeline of NW*G waves:
+// slot j goes to group (j / NW) mod G, wave j mod NW.  Wave 0's predecessor slot then
+// sits in wave NW-1 of the previous group, another workgroup: that wave
+// publishes its progress in gprog[its group] (global memory, agent-scope
+// release, after its tiles have gone to Z) and wave 0 waits on it with an
+// agent-scope acquire.  The G workgroups of a strip must run concurrently
+// (a cooperative launch).
+//
 // With CKPT (the first pass of the adjoint), every block's input window is
 // also written to ckpt (non-temporal stores: read once, much later, so they
 // should not displace the operand stream in the caches), one 16x16 tile at a
@@ -715,7 +745,9 @@ __device__ __attribute__((always_inline)) inline void blocked_strip(int64_t n, i
                                      double* __restrict__ Z, int64_t ldz,
                                      unsigned* __restrict__ err, int64_t strip,
                                      StripLds<NB, CT, CPLX, NW>& S,
-                                     double* __restrict__ ckpt = nullptr, int64_t nstrips = 0)
+                                     double* __restrict__ ckpt = nullptr, int64_t nstrips = 0,
+                                     int ngroups = 1, int grp = 0,
+                                     int* __restrict__ gprog = nullptr)
 {
     constexpr int XR = StripLds<NB, CT, CPLX, NW>::R;
     int* prog = S.prog;
@@ -741,8 +773,16 @@ __device__ __attribute__((always_inline)) inline void blocked_strip(int64_t n, i
 
     Tile<CPLX> zt[NT][CT];
     double ring_re[D], ring_im[D];
+    // the predecessor of this wave's slots: wave w-1 of this workgroup, or
+    // (wave 0 with slot groups) wave NW-1 of the previous group
+    const bool pred_global = ngroups > 1 && w == 0;
+    const int* gpred = pred_global ? gprog + (grp + ngroups - 1) % ngroups : nullptr;
+    auto wait_pred = [&](int need) -> bool {
+        return pred_global ? wait_global(gpred, need, err, lane, seen_prog)
+                           : wait_counter(prog, wprev, need, err, lane, seen_prog);
+    };
 
-    for (int64_t j = w; j < J; j += NW) {
+    for (int64_t j = (int64_t)grp * NW + w; j < J; j += (int64_t)NW * ngroups) {
         const int64_t t0 = j * nt1;
         // the slot's operand stream; blocks are PB doubles apart
         const __amdgpu_buffer_rsrc_t ops =
@@ -750,8 +790,7 @@ __device__ __attribute__((always_inline)) inline void blocked_strip(int64_t n, i
                         (uint32_t)((nblk - t0) * G::PB * sizeof(double)));
         uint32_t boff = 0;
         const int need0 = (int)((j - 1) * (nblk + 1));   // + t + 1: slot j-1 done block t
-        if (j > 0 && !wait_counter(prog, wprev, need0 + (int)t0 + 1, err, lane, seen_prog))
-            return;
+        if (j > 0 && !wait_pred(need0 + (int)t0 + 1)) return;
         int64_t p0 = n - 3 - KB * t0 - 15 + j * NB;
         // first block of the slot: window tile q in register tile q
 #pragma unroll
@@ -780,9 +819,7 @@ __device__ __attribute__((always_inline)) inline void blocked_strip(int64_t n, i
                 lds_get<CPLX, CT>(znext, &S.ring[w - 1][xget % XR][0], lane);
                 ++xget;
             } else if (has_next) {
-                if (j > 0 &&
-                    !wait_counter(prog, wprev, need0 + (int)t + 2, err, lane, seen_prog))
-                    return;
+                if (j > 0 && !wait_pred(need0 + (int)t + 2)) return;
                 const bool inside = cols_inside && p0 - 16 >= 0 && p0 <= n;
 #pragma unroll
                 for (int c = 0; c < CT; ++c)
@@ -990,6 +1027,9 @@ __device__ __attribute__((always_inline)) inline void blocked_strip(int64_t n, i
                                    __HIP_MEMORY_SCOPE_WORKGROUP);
             __hip_atomic_store(&prog[w], (int)(j * (nblk + 1) + t + 1), __ATOMIC_RELEASE,
                                __HIP_MEMORY_SCOPE_WORKGROUP);
+            if (ngroups > 1 && w == NW - 1)   // the next group's wave 0 waits on this
+                __hip_atomic_store(&gprog[grp], (int)(j * (nblk + 1) + t + 1), __ATOMIC_RELEASE,
+                                   __HIP_MEMORY_SCOPE_AGENT);
             if constexpr (CPLX) {
                 rot = ret;
             } else if (has_next) {
@@ -1004,17 +1044,33 @@ __device__ __attribute__((always_inline)) inline void blocked_strip(int64_t n, i
     }
 }
 
+// One workgroup per (strip, slot group).  With G > 1 the G workgroups of a
+// strip are numbered so that they land on one XCD (workgroups are handed to
+// the 8 XCDs in turn): workgroup b is XCD b % 8's (b / 8)-th, strip
+// ((b / 8) / G) * 8 + b % 8, group (b / 8) % G; the grid is padded to a
+// multiple of 8 strips and the workgroups of padding strips leave at once.
+// gprog: G progress counters per strip (zero on entry).
 template <int NB, int CT, bool CPLX, int D, int NW>
 __global__ __launch_bounds__(64 * NW) void k_blocked(int64_t n, int64_t nev,
                                                      const double* __restrict__ ws,
                                                      double* __restrict__ Z, int64_t ldz,
-                                                     unsigned* __restrict__ err)
+                                                     unsigned* __restrict__ err, int G,
+                                                     int* __restrict__ gprog)
 {
     __shared__ StripLds<NB, CT, CPLX, NW> S;
+    int64_t strip = blockIdx.x;
+    int g = 0;
+    if (G > 1) {
+        const int64_t i = blockIdx.x / 8;
+        strip = (i / G) * 8 + blockIdx.x % 8;
+        g = (int)(i % G);
+        if (strip * 16 * CT >= nev) return;
+    }
     S.reset();
     __syncthreads();
     blocked_strip<NB, CT, CPLX, D, NW>(n, nev, ws + HDR_BYTES / sizeof(double), Z, ldz, err,
-                                       blockIdx.x, S);
+                                       strip, S, nullptr, 0, G, g,
+                                       G > 1 ? gprog + strip * G : nullptr);
 }
 
 __global__ void k_zero_words(unsigned* p, int count)

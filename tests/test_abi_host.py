@@ -108,18 +108,24 @@ def test_workspace_query(T):
         T.trbt_workspace_bytes(10, 300, 1, False)
 
 
-@pytest.mark.parametrize("n,nbw", [(1000, 64), (2000, 32), (777, 48), (300, 16), (66, 64)])
-def test_workspace_size_is_the_packed_layout(T, oracle_mod, n, nbw):
+@pytest.mark.parametrize("n,nbw", [(1000, 64), (2000, 32), (777, 48), (300, 16), (66, 64),
+                                   (1000, 128), (500, 80)])
+@pytest.mark.parametrize("nev_frac", [0, 3])
+def test_workspace_size_is_the_packed_layout(T, oracle_mod, n, nbw, nev_frac):
     """Blocked shapes: a 256-byte header plus, for every (slot j, 16-stage
     block t >= j*nbw/16), the two MFMA operand matrices of the block's
-    compact-WY factor, (nbw+16) x 16 each, one plane real, two complex."""
+    compact-WY factor, (nbw+16) x 16 each, one plane real, two complex;
+    then the slot-group progress counters, 8 ints for each 16-column strip
+    and for 8 strips of padding, rounded up to 256 bytes."""
+    nev = n // nev_frac if nev_frac else 10
     st = oracle_mod.reflector_table(n, nbw)[0]
     J = int(np.sum(st == 0))                   # slots of stage 0
     nblk = -(-(n - 2) // 16)
     nblocks = sum(nblk - j * (nbw // 16) for j in range(J))
+    counters = -(-((-(-nev // 16) + 8) * 8 * 4) // 256) * 256
     for cplx, planes in ((False, 1), (True, 2)):
-        expect = 256 + nblocks * 2 * (nbw + 16) * 16 * planes * 8
-        assert T.trbt_workspace_bytes(n, nbw, 10, cplx) == expect, (n, nbw, cplx)
+        expect = 256 + nblocks * 2 * (nbw + 16) * 16 * planes * 8 + counters
+        assert T.trbt_workspace_bytes(n, nbw, nev, cplx) == expect, (n, nbw, cplx)
 
 
 def test_strerror(T):

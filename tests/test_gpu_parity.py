@@ -109,6 +109,20 @@ def test_ldz_padding_untouched_and_nan_isolated(oracle_mod, dtype):
     assert np.all(np.isfinite(out[good, :n]))
 
 
+@pytest.mark.parametrize("dtype", ["d", "z"])
+@pytest.mark.parametrize("n,nbw,nev", [(2000, 16, 50), (3000, 32, 100), (1500, 64, 300),
+                                       (2500, 48, 17), (3000, 128, 40), (1024, 32, 1024)])
+def test_parity_slot_groups(oracle_mod, dtype, n, nbw, nev):
+    """Few column strips and many slots: several workgroups share each strip
+    (slot groups, up to 8), handing tiles across workgroups through Z."""
+    Z, V, tau = _inputs(n, nbw, nev, dtype, 6000 + n + nbw, oracle_mod)
+    ref = oracle_mod.back_transform(Z, V, tau, nbw)
+    out, _ = gpu_back_transform(Z, V, tau, nbw)
+    assert _relerr(out[:, :n].T, ref) <= TOL
+    again, _ = gpu_back_transform(Z, V, tau, nbw)
+    assert np.array_equal(out.view(np.uint8), again.view(np.uint8))
+
+
 @pytest.mark.parametrize("nbw", [32, 7])
 def test_deterministic_bitwise(oracle_mod, nbw):
     Z, V, tau = _inputs(257, nbw, 50, "z", 5, oracle_mod)
