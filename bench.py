@@ -611,6 +611,80 @@ def b2f_leg(steps: int, warmup: int, cpu: bool = True):
     return res
 
 
+def shapes_leg(steps: int, warmup: int, names=("C1", "C2", "C3s", "C3w")):
+    """The other single-problem shapes, each timed like the headline step
+    (prepare + apply through the C ABI, HIP events on the stream): the two
+    real workloads (C1 n=1024 nbw=32 nev=1024, C2 n=8192 nbw=64 nev=4096),
+    one GPU's column share of the headline shape split over eight (C3s,
+    nev=1024) and the headline size with nbw=128 (C3w).  Roofline of the
+    apply kernel against the FP64 peak; algorithmic flops c*nev*L."""
+    import torch
+    import paper_2002_10991_amd as T
+    dev = torch.device("cuda:0")
+    stream = torch.cuda.current_stream()
+    res = {}
+    for name in names:
+        cfg = WORKLOADS[name]
+        n, nbw, nev, dt = cfg["n"], cfg["nbw"], cfg["nev"], cfg["dtype"]
+        cplx = dt == "z"
+        t = time.perf_counter()
+        lengths, V, tau, Z = make_inputs(cfg)
+        L_total = int(lengths.sum())
+        Vd = torch.from_numpy(V).to(dev)
+        td = torch.from_numpy(tau).to(dev)
+        Zbuf = torch.from_numpy(np.ascontiguousarray(Z.T)).to(dev)
+        del V, Z
+        work = T.alloc_workspace(n, nbw, nev, cplx, dev)
+        wb = 0 if work is None else work.numel()
+        prep = T.trbt_prepare_z if cplx else T.trbt_prepare_d
+        appl = T.trbt_apply_z if cplx else T.trbt_apply_d
+        log(f"shape {name}: inputs ready in {time.perf_counter() - t:.1f}s")
+
+        def step(ev=None):
+            if ev:
+                ev[0].record(stream)
+            if prep(n, nbw, Vd, td, work, wb, stream):
+                raise RuntimeError(f"{name}: prepare failed")
+            if ev:
+                ev[1].record(stream)
+            if appl(n, nbw, nev, Vd, td, Zbuf, n, work, wb, stream):
+                raise RuntimeError(f"{name}: apply failed")
+            if ev:
+                ev[2].record(stream)
+
+        for _ in range(max(warmup, 1)):
+            step()
+        torch.cuda.synchronize()
+        k = max(steps, 3)
+        evs = [[torch.cuda.Event(enable_timing=True) for _ in range(3)] for _ in range(k)]
+        t0 = time.perf_counter()
+        for e in evs:
+            step(e)
+        torch.cuda.synchronize()
+        ms = (time.perf_counter() - t0) / k * 1e3
+        if work is not None and T.trbt_work_check(work):
+            raise RuntimeError(f"{name}: device wait-timeout flag set")
+        apply_ms = float(np.mean([e[1].elapsed_time(e[2]) for e in evs]))
+        flops = (16 if cplx else 4) * nev * L_total
+        strips = -(-nev // 16)
+        res[name] = {
+            "n": n, "nbw": nbw, "nev": nev, "dtype": "c128" if cplx else "f64",
+            "ms_per_step": round(ms, 3), "apply_ms": round(apply_ms, 3),
+            "tflops_per_step": round(flops / (ms / 1e3) / 1e12, 4),
+            "roofline": {"bound": "mfma",
+                         "achieved": round(flops / (apply_ms / 1e3) / 1e12, 4),
+                         "peak": PEAK_FP64_TFLOPS, "unit": "TFLOP/s",
+                         "frac": round(flops / (apply_ms / 1e3) / 1e12 / PEAK_FP64_TFLOPS, 4),
+                         "kernel": "k_blocked (apply)"},
+            "column_strips": strips,
+        }
+        log(f"shape {name}: {ms:.3f} ms per step, apply {apply_ms:.3f} ms, "
+            f"{res[name]['roofline']['achieved']} TFLOP/s")
+        del Vd, td, Zbuf, work
+        torch.cuda.empty_cache()
+    return res
+
+
 def committed_traffic(workload: str):
     """HBM bytes per launch of the apply kernel from the committed rocprofv3
     counter summary, if it was taken on the current kernel source; else None."""
@@ -638,6 +712,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", default="C3", choices=sorted(WORKLOADS))
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-shapes", action="store_true",
+                    help="skip the other single-problem shapes (C1, C2, C3s, C3w)")
     ap.add_argument("--no-batched", action="store_true",
                     help="skip the batched-vs-looped comparison on the 64-problem workload")
     ap.add_argument("--batched-only", action="store_true",
@@ -791,6 +867,8 @@ def main():
             "kernel": "k_blocked (apply)",
         },
     }
+    if not args.no_shapes:
+        out["shapes"] = shapes_leg(min(args.steps, 10), args.warmup)
     if not args.no_batched:
         out["batched_vs_loop"] = batched_leg(args.steps, args.warmup)
         out["batched_complex_vs_loop"] = batched_leg(args.steps, args.warmup, "z")

@@ -14,9 +14,9 @@
 //  * k_b2f_tfac (one workgroup per panel): the Gram matrix V^H V on FP64
 //    MFMA, then T column by column, T[0:q, q] = -tau_q T[0:q, 0:q] G[0:q, q],
 //    stored column-major (PW x PW) in the workspace.
-//  * k_b2f_apply (one workgroup per strip of 16 CT columns of Z, 8 waves):
+//  * k_b2f_apply (one workgroup per strip of 16 CT columns of Z, NW waves):
 //    for every panel p from the last to the first, the waves walk the
-//    panel's rows in 16-row blocks (block b to wave b mod 8).  A block is
+//    panel's rows in 16-row blocks (block b to wave b mod NW).  A block is
 //    loaded once into MFMA accumulators, updated with panel p
 //    (Z -= V_p W'_p, W'_p in LDS), stored, and -- while still in registers --
 //    contracted with the next panel's reflectors, W_{p-1} += V_{p-1}^H Z.
@@ -102,6 +102,22 @@ __device__ inline Elt<CPLX> v_at(const double* __restrict__ V, int64_t ldv, int6
 {
     Elt<CPLX> e{};
     if (j < J && r >= j + nbw && r < n) e = ld_elt<CPLX>(V, r + j * ldv);
+    return e;
+}
+
+// The same without a branch: the load reads a clamped address inside the
+// n x J array (row min(r, n-1), column min(j, J-1)) and the value is
+// replaced by 0 where the reflector has no entry, so a block's loads can all
+// be issued before the first is needed.
+template <bool CPLX>
+__device__ inline Elt<CPLX> v_sel(const double* __restrict__ V, int64_t ldv, int64_t n,
+                                  int nbw, int64_t J, int64_t r, int64_t j)
+{
+    const bool ok = j < J && r >= j + nbw && r < n;
+    const int64_t rr = r < n ? r : n - 1, jj = j < J ? j : J - 1;
+    Elt<CPLX> e = ld_elt<CPLX>(V, rr + jj * ldv);
+    e.re = ok ? e.re : 0.0;
+    if constexpr (CPLX) e.im = ok ? e.im : 0.0;
     return e;
 }
 
@@ -226,12 +242,12 @@ struct B2FLds {
     double Wp[B2F_PT][CT][4][CPLX ? 2 : 1][64];
 };
 
-template <bool CPLX, int CT>
-__global__ __launch_bounds__(64 * B2F_NW) void k_b2f_apply(
+template <bool CPLX, int CT, int NW>
+__global__ __launch_bounds__(64 * NW) void k_b2f_apply(
     int64_t n, int nbw, int64_t nev, const double* __restrict__ V, int64_t ldv,
     const double* __restrict__ Tw, double* __restrict__ Z, int64_t ldz)
 {
-    constexpr int PW = B2F_PW, PT = B2F_PT, NW = B2F_NW, NP = CPLX ? 2 : 1;
+    constexpr int PW = B2F_PW, PT = B2F_PT, NP = CPLX ? 2 : 1;
     __shared__ B2FLds<CPLX, CT> S;
     const int64_t J = b2f_reflectors(n, nbw);
     const int64_t P = b2f_panels(J);
@@ -303,25 +319,65 @@ __global__ __launch_bounds__(64 * B2F_NW) void k_b2f_apply(
         const int64_t lo = (p > 0) ? jn + nbw : jp + nbw;
         const bool upd = p < P, acc = p > 0;
         for (int64_t r0 = lo + 16 * (int64_t)wv; r0 < n; r0 += 16 * NW) {
+            // W'_p is read from LDS block by block, not held in registers
+            // across the loop (room for the block's operands)
+            asm volatile("" ::: "memory");
+            // every load of the block first (clamped addresses, masked
+            // values), then the products
             Tile<CPLX> z[CT];
-            // load the 16-row block: lane (j, g) element e = Z[r0+g+4e][col0+16c+j]
+            // the 16-row block: lane (j, g) element e = Z[r0+g+4e][col0+16c+j]
 #pragma unroll
             for (int c = 0; c < CT; ++c) {
                 const int64_t col = col0 + 16 * c + i16;
+                const int64_t cc = col < nev ? col : nev - 1;
 #pragma unroll
                 for (int e = 0; e < 4; ++e) {
                     const int64_t r = r0 + g4 + 4 * e;
-                    Elt<CPLX> x{};
-                    if (r < n && col < nev) x = ld_elt<CPLX>(Z, r + col * ldz);
-                    z[c].re[e] = x.re;
-                    if constexpr (CPLX) z[c].im[e] = x.im;
+                    const bool ok = r < n && col < nev;
+                    const Elt<CPLX> x = ld_elt<CPLX>(Z, (r < n ? r : n - 1) + cc * ldz);
+                    z[c].re[e] = ok ? x.re : 0.0;
+                    if constexpr (CPLX) z[c].im[e] = ok ? x.im : 0.0;
                 }
             }
             const bool in_p = upd && r0 >= jp + nbw;
+            // Real blocks load all of their reflector operands before the
+            // first product (one MFMA per operand: latency would dominate);
+            // complex blocks (four MFMAs per operand, and no registers to
+            // spare) load each operand just before its products.
+            constexpr bool HOIST = !CPLX;
+            constexpr int NU = HOIST ? PW / 4 : 1, NA = HOIST ? 4 : 1, NPT = HOIST ? PT : 1;
+            // update operands: A[i][k] = V[r0+i][jp+4kk+k]
+            Elt<CPLX> vu[NU];
+            // accumulation operands: A[i][k] = conj(V[r0+4u+k][jn+16a+i])
+            Elt<CPLX> va[NA][NPT];
+            if constexpr (HOIST) {
+                if (in_p) {
+#pragma unroll
+                    for (int kk = 0; kk < PW / 4; ++kk)
+                        vu[kk] = v_sel<CPLX>(V, ldv, n, nbw, J, r0 + i16, jp + 4 * kk + g4);
+                }
+                if (acc) {
+#pragma unroll
+                    for (int u = 0; u < 4; ++u)
+#pragma unroll
+                        for (int a = 0; a < PT; ++a)
+                            va[u][a] = v_sel<CPLX>(V, ldv, n, nbw, J, r0 + 4 * u + g4,
+                                                   jn + 16 * a + i16);
+                }
+            }
+            auto v_upd = [&](int kk) -> Elt<CPLX> {
+                if constexpr (HOIST) return vu[kk];
+                else return v_at<CPLX>(V, ldv, n, nbw, J, r0 + i16, jp + 4 * kk + g4);
+            };
+            auto v_acc = [&](int u, int a) -> Elt<CPLX> {
+                if constexpr (HOIST) return va[u][a];
+                else return v_at<CPLX>(V, ldv, n, nbw, J, r0 + 4 * u + g4, jn + 16 * a + i16);
+            };
             if (in_p) {
                 // Z -= V_p W'_p: A[i][k] = V[r0+i][jp+k0+k], B = W'_p rows k0..k0+3
+#pragma unroll
                 for (int k0 = 0; k0 < PW; k0 += 4) {
-                    const Elt<CPLX> v = v_at<CPLX>(V, ldv, n, nbw, J, r0 + i16, jp + k0 + g4);
+                    const Elt<CPLX> v = v_upd(k0 / 4);
                     const int bt = k0 / 16, be = (k0 % 16) / 4;
 #pragma unroll
                     for (int c = 0; c < CT; ++c) {
@@ -357,8 +413,7 @@ __global__ __launch_bounds__(64 * B2F_NW) void k_b2f_apply(
                 for (int u = 0; u < 4; ++u) {
 #pragma unroll
                     for (int a = 0; a < PT; ++a) {
-                        const Elt<CPLX> v =
-                            v_at<CPLX>(V, ldv, n, nbw, J, r0 + 4 * u + g4, jn + 16 * a + i16);
+                        const Elt<CPLX> v = v_acc(u, a);
 #pragma unroll
                         for (int c = 0; c < CT; ++c) {
                             w[a][c].re = mfma(v.re, z[c].re[u], w[a][c].re);
@@ -418,15 +473,21 @@ int b2f_run(int64_t n, int nbw, int64_t nev, const double* V, int64_t ldv, const
     const int64_t P = b2f_panels(J);
     hipLaunchKernelGGL((k_b2f_tfac<CPLX>), dim3((unsigned)P), dim3(256), 0, st, n, nbw, V, ldv,
                        tau, Tw);
-    // two 16-column tiles per workgroup when that still gives every CU a strip
+    // complex: two 16-column tiles per workgroup when that still gives every
+    // CU a strip; real: one (its block operands take the registers)
     const int64_t s2 = (nev + 31) / 32;
-    if (s2 >= 256) {
-        hipLaunchKernelGGL((k_b2f_apply<CPLX, 2>), dim3((unsigned)s2), dim3(64 * B2F_NW), 0, st,
-                           n, nbw, nev, V, ldv, (const double*)Tw, Z, ldz);
-    } else {
+    if constexpr (CPLX) {
+        if (s2 >= 256) {
+            hipLaunchKernelGGL((k_b2f_apply<CPLX, 2, B2F_NW>), dim3((unsigned)s2),
+                               dim3(64 * B2F_NW), 0, st, n, nbw, nev, V, ldv, (const double*)Tw,
+                               Z, ldz);
+            return hipGetLastError() == hipSuccess ? TRBT_SUCCESS : TRBT_ERR_HIP;
+        }
+    }
+    {
         const int64_t s1 = (nev + 15) / 16;
-        hipLaunchKernelGGL((k_b2f_apply<CPLX, 1>), dim3((unsigned)s1), dim3(64 * B2F_NW), 0, st,
-                           n, nbw, nev, V, ldv, (const double*)Tw, Z, ldz);
+        hipLaunchKernelGGL((k_b2f_apply<CPLX, 1, B2F_NW>), dim3((unsigned)s1), dim3(64 * B2F_NW),
+                           0, st, n, nbw, nev, V, ldv, (const double*)Tw, Z, ldz);
     }
     return hipGetLastError() == hipSuccess ? TRBT_SUCCESS : TRBT_ERR_HIP;
 }

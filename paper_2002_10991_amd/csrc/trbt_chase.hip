@@ -31,9 +31,10 @@
 // checks of this schedule against the traced sequential footprints, over
 // stage distances 1-5 and ragged ends, find no other overlap.)  Each stage is
 // run start to finish by one workgroup (stages are dealt in increasing order
-// from a ticket counter), which publishes its progress after every step with
-// an agent-scope release and waits for its predecessor's with an agent-scope
-// acquire.  A stage only ever waits on a stage whose ticket was taken earlier
+// from a ticket counter), which publishes its progress after every step
+// and waits for its predecessor's, the band being read and written with
+// device-coherent accesses (so neither side needs a fence over the whole
+// cache).  A stage only ever waits on a stage whose ticket was taken earlier
 // by a workgroup that is running, so the wait always ends; it is bounded
 // anyway (a wall-clock limit that sets an error flag and makes every
 // workgroup leave).
@@ -129,6 +130,27 @@ __device__ inline void stx(double* p, cx v)
 {
     p[0] = v.re;
     if constexpr (C) p[1] = v.im;
+}
+
+// Device-coherent (agent-scope relaxed atomic) access to the band: every
+// entry a step reads may have been written by another stage's workgroup on
+// another CU (and another XCD's L2), and every entry it writes may be read
+// by one; ordering comes from the progress counters (see the step's end).
+template <bool C>
+__device__ inline cx ldx_coh(const double* p)
+{
+    double* q = const_cast<double*>(p);
+    cx v;
+    v.re = __hip_atomic_load(q, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    v.im = C ? __hip_atomic_load(q + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) : 0.0;
+    return v;
+}
+
+template <bool C>
+__device__ inline void stx_coh(double* p, cx v)
+{
+    __hip_atomic_store(p, v.re, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    if constexpr (C) __hip_atomic_store(p + 1, v.im, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
 template <bool C>
@@ -249,7 +271,6 @@ __global__ __launch_bounds__(64 * NW) void k_chase(int64_t n, int b,
             if (s > 0 && j == 0) {
                 if (threadIdx.x == 0) {
                     fail_sh = !chase_wait(&prog[s - 1], (int)(j + 2 < Sp ? j + 2 : Sp), ctl);
-                    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
                 }
                 __syncthreads();
                 if (fail_sh) return;
@@ -271,20 +292,31 @@ __global__ __launch_bounds__(64 * NW) void k_chase(int64_t n, int b,
             cx x = {0.0, 0.0};
             if (w == 0) {
                 if (j > 0) x = car[0];
-                else if (lane < len) x = ldx<C>(at(r0 + lane, c));
+                else if (lane < len) x = ldx_coh<C>(at(r0 + lane, c));
             }
             cx yl[COLS], yr[COLS], ad[COLS];
+            // every lane issues every load (from a valid dummy address where
+            // it has no entry), so the loads of all columns are in flight
+            // together instead of one masked load and its wait at a time
 #pragma unroll
             for (int t = 0; t < COLS; ++t) {
                 const int m = w + NW * t;
-                yr[t] = ad[t] = cx{0.0, 0.0};
                 yl[t] = (j > 0 && m >= 1) ? car[t] : cx{0.0, 0.0};
                 // (the corner is read in the tail: step (s-1, j+2) may be
                 // writing it now)
-                if (m < len && lane < nr && !(crow && m == b - 1))
-                    yr[t] = ldx<C>(at(r0 + len + lane, r0 + m));
-                if (m < len && lane >= m && lane < len) {
-                    ad[t] = ldx<C>(at(r0 + lane, r0 + m));
+                const bool okr = m < len && lane < nr && !(crow && m == b - 1);
+                const bool okd = m < len && lane >= m && lane < len;
+                yr[t] = ldx_coh<C>(okr ? at(r0 + len + lane, r0 + m) : bd);
+                ad[t] = ldx_coh<C>(okd ? at(r0 + lane, r0 + m) : bd);
+            }
+#pragma unroll
+            for (int t = 0; t < COLS; ++t) {
+                const int m = w + NW * t;
+                const bool okr = m < len && lane < nr && !(crow && m == b - 1);
+                const bool okd = m < len && lane >= m && lane < len;
+                if (!okr) yr[t] = cx{0.0, 0.0};
+                if (!okd) ad[t] = cx{0.0, 0.0};
+                if (okd) {
                     stx<C>(&As[(m * CH_PITCH + lane) * E], ad[t]);
                     if (lane > m) stx<C>(&As[(lane * CH_PITCH + m) * E], cx{ad[t].re, -ad[t].im});
                 }
@@ -323,7 +355,7 @@ __global__ __launch_bounds__(64 * NW) void k_chase(int64_t n, int b,
                     stx<C>(ht + kref * E, tau);
                 }
                 if (lane < b) stx<C>(hv + (kref * b + lane) * E, v);
-                if (lane < len) stx<C>(at(r0 + lane, c), lane == 0 ? cx{beta, 0.0} : cx{0.0, 0.0});
+                if (lane < len) stx_coh<C>(at(r0 + lane, c), lane == 0 ? cx{beta, 0.0} : cx{0.0, 0.0});
             }
             __syncthreads();
 
@@ -341,7 +373,7 @@ __global__ __launch_bounds__(64 * NW) void k_chase(int64_t n, int b,
                     if (j > 0 && m >= 1 && m < b) {
                         const cx f = cmulc<C>(tau, dot[t]);           // conj(tau) (v^H y)
                         yl[t] = csub<C>(yl[t], cmul<C>(f, vi));
-                        if (lane < len) stx<C>(at(r0 + lane, c + m), yl[t]);
+                        if (lane < len) stx_coh<C>(at(r0 + lane, c + m), yl[t]);
                     }
                 }
             }
@@ -378,11 +410,11 @@ __global__ __launch_bounds__(64 * NW) void k_chase(int64_t n, int b,
                     const cx vm = ldx<C>(&vs[m * E]);
                     if (!crow) {
                         yr[t] = csub<C>(yr[t], cmul_cb<C>(tz, vm));
-                        if (!has_next && lane < nr) stx<C>(at(r0 + len + lane, r0 + m), yr[t]);
+                        if (!has_next && lane < nr) stx_coh<C>(at(r0 + len + lane, r0 + m), yr[t]);
                     }
                     const cx wm = shfl_x<C>(wv, m);
                     ad[t] = csub<C>(ad[t], cadd<C>(cmul_cb<C>(wv, vm), cmul_cb<C>(vi, wm)));
-                    if (lane >= m && lane < len) stx<C>(at(r0 + lane, r0 + m), ad[t]);
+                    if (lane >= m && lane < len) stx_coh<C>(at(r0 + lane, r0 + m), ad[t]);
                 }
             }
 
@@ -395,7 +427,6 @@ __global__ __launch_bounds__(64 * NW) void k_chase(int64_t n, int b,
             if (s > 0) {
                 if (threadIdx.x == 0) {
                     fail_sh = !chase_wait(&prog[s - 1], (int)(j + 3 < Sp ? j + 3 : Sp), ctl);
-                    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
                 }
                 __syncthreads();
                 if (fail_sh) return;
@@ -404,7 +435,7 @@ __global__ __launch_bounds__(64 * NW) void k_chase(int64_t n, int b,
                 const cx vb = ldx<C>(&vs[(b - 1) * E]);
                 cx zc = z;
                 if (crow) {
-                    const cx cv = ldx<C>(at(r0 + 2 * (int64_t)b - 1, r0 + b - 1));
+                    const cx cv = ldx_coh<C>(at(r0 + 2 * (int64_t)b - 1, r0 + b - 1));
                     zc = cadd<C>(z, cmul<C>(cv, vb));
 #pragma unroll
                     for (int t = 0; t < COLS; ++t) {
@@ -418,21 +449,24 @@ __global__ __launch_bounds__(64 * NW) void k_chase(int64_t n, int b,
                     const int m = w + NW * t;
                     if (m < len && crow) {
                         yr[t] = csub<C>(yr[t], cmul_cb<C>(tzc, ldx<C>(&vs[m * E])));
-                        if (!has_next) stx<C>(at(r0 + len + lane, r0 + m), yr[t]);
+                        if (!has_next) stx_coh<C>(at(r0 + len + lane, r0 + m), yr[t]);
                     }
                 }
             }
 #pragma unroll
             for (int t = 0; t < COLS; ++t) car[t] = yr[t];
 
-            // publish the step: every wave waits until its stores have
-            // reached L2, then one agent-scope release (one write-back of
-            // the L2) covers the whole workgroup's stores
-            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
-            __builtin_amdgcn_s_waitcnt(0);
+            // publish the step: every wave waits until its (device-coherent)
+            // stores have completed, then one counter store.  A waiting
+            // stage reads the counter, then -- after a barrier -- the band
+            // with device-coherent loads, so it sees every store made
+            // before the counter.  (Agent-scope release and acquire fences
+            // would write back and invalidate the whole L2 of the XCD at
+            // every step.)
+            asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
             __syncthreads();
             if (threadIdx.x == 0)
-                __hip_atomic_store(&prog[s], (int)(j + 1), __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+                __hip_atomic_store(&prog[s], (int)(j + 1), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         }
     }
 }

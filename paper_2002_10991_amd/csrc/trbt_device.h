@@ -458,14 +458,49 @@ __device__ inline d4 mfma_n(double a, double b, d4 c)
     return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, NEG);
 }
 
+// Device-coherent (agent-scope relaxed atomic) loads and stores of single
+// elements: for tiles handed from one workgroup to another, which may run on
+// another CU and another XCD's L2.
+__device__ inline double ld_coh(const double* p)
+{
+    return __hip_atomic_load(const_cast<double*>(p), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+__device__ inline void st_coh(double* p, double v)
+{
+    __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
 // Tile load.  Interior tiles (all rows inside the matrix, whole strip inside
 // nev: a wave-uniform test) load directly; edge tiles read a clamped, valid
 // address and zero what lies outside, so all loads issue back to back.
+// coh (wave-uniform): device-coherent loads of a tile another workgroup
+// stored with store_tile(..., coh = true).
 template <bool CPLX>
 __device__ inline void load_tile(Tile<CPLX>& t, const double* __restrict__ Z, int64_t ldz,
                                  int64_t n, int64_t nev, int64_t row0, int64_t col,
-                                 bool interior)
+                                 bool interior, bool coh = false)
 {
+    if (coh) {
+        const bool colok = col < nev;
+        const int64_t cc = colok ? col : nev - 1;
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+            const int64_t r = row0 + 4 * e;
+            const bool ok = colok && r >= 0 && r < n;
+            const int64_t rr = r < 0 ? 0 : (r >= n ? n - 1 : r);
+            if constexpr (CPLX) {
+                const double xr = ld_coh(Z + 2 * (cc * ldz + rr));
+                const double xi = ld_coh(Z + 2 * (cc * ldz + rr) + 1);
+                t.re[e] = ok ? xr : 0.0;
+                t.im[e] = ok ? xi : 0.0;
+            } else {
+                const double x = ld_coh(Z + cc * ldz + rr);
+                t.re[e] = ok ? x : 0.0;
+            }
+        }
+        return;
+    }
     if (interior) {
 #pragma unroll
         for (int e = 0; e < 4; ++e) {
@@ -503,8 +538,24 @@ __device__ inline void load_tile(Tile<CPLX>& t, const double* __restrict__ Z, in
 template <bool CPLX>
 __device__ inline void store_tile(const Tile<CPLX>& t, double* __restrict__ Z, int64_t ldz,
                                   int64_t n, int64_t nev, int64_t row0, int64_t col,
-                                  bool interior = false)
+                                  bool interior = false, bool coh = false)
 {
+    if (coh) {   // device-coherent stores (read by another workgroup)
+        if (col >= nev) return;
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+            const int64_t r = row0 + 4 * e;
+            if (r >= 0 && r < n) {
+                if constexpr (CPLX) {
+                    st_coh(Z + 2 * (col * ldz + r), t.re[e]);
+                    st_coh(Z + 2 * (col * ldz + r) + 1, t.im[e]);
+                } else {
+                    st_coh(Z + col * ldz + r, t.re[e]);
+                }
+            }
+        }
+        return;
+    }
     if (interior) {
 #pragma unroll
         for (int e = 0; e < 4; ++e) {
@@ -589,8 +640,12 @@ __device__ inline bool wait_counter(int* ctr, int idx, int need, unsigned* err, 
 }
 
 // The same wait on a progress counter in global memory, published by a wave
-// of another workgroup with an agent-scope release; the acquire that ends
-// the wait makes that workgroup's earlier stores to Z visible here.
+// of another workgroup (publish_global).  The data that workgroup handed
+// over was stored device-coherently before the counter and is read
+// device-coherently after it: the counter load has returned (and been
+// waited for) before any of those loads issues, and the compiler may not
+// move them above the wait.  (An agent-scope acquire fence would instead
+// invalidate the whole L2 of this XCD each time.)
 __device__ inline bool wait_global(const int* ctr, int need, unsigned* err, int lane, int& seen)
 {
     wait_jitter(need, need);
@@ -604,9 +659,19 @@ __device__ inline bool wait_global(const int* ctr, int need, unsigned* err, int 
             return false;
         }
     }
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+    asm volatile("" ::: "memory");
     seen = v;
     return true;
+}
+
+// Publish a progress value for another workgroup: every earlier memory
+// operation of this wave (among them the device-coherent tile stores it
+// hands over) completes first, then the counter is stored device-coherently.
+// (An agent-scope release would write back the whole L2 of this XCD.)
+__device__ inline void publish_global(int* ctr, int val)
+{
+    asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
+    __hip_atomic_store(ctr, val, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
 // Operand ring depth (chunks loaded ahead of use).  The ring position of a
@@ -729,8 +794,9 @@ __device__ inline void lds_get(Tile<CPLX> (&t)[CT], const double* __restrict__ s
 // slot j goes to group (j / NW) mod G, wave j mod NW.  Wave 0's predecessor slot then
 // sits in wave NW-1 of the previous group, another workgroup: that wave
 // publishes its progress in gprog[its group] (global memory, agent-scope
-// release, after its tiles have gone to Z) and wave 0 waits on it with an
-// agent-scope acquire.  The G workgroups of a strip must run concurrently
+// publish_global, after its tiles have gone to Z with device-coherent
+// stores) and wave 0 waits on it (wait_global) and reads those tiles with
+// device-coherent loads.  The G workgroups of a strip must run concurrently
 // (a cooperative launch).
 //
 // With CKPT (the first pass of the adjoint), every block's input window is
@@ -776,6 +842,7 @@ __device__ __attribute__((always_inline)) inline void blocked_strip(int64_t n, i
     // the predecessor of this wave's slots: wave w-1 of this workgroup, or
     // (wave 0 with slot groups) wave NW-1 of the previous group
     const bool pred_global = ngroups > 1 && w == 0;
+    const bool coh_out = ngroups > 1 && w == NW - 1;   // this wave's tiles go to another group
     const int* gpred = pred_global ? gprog + (grp + ngroups - 1) % ngroups : nullptr;
     auto wait_pred = [&](int need) -> bool {
         return pred_global ? wait_global(gpred, need, err, lane, seen_prog)
@@ -799,7 +866,7 @@ __device__ __attribute__((always_inline)) inline void blocked_strip(int64_t n, i
 #pragma unroll
             for (int c = 0; c < CT; ++c)
                 load_tile<CPLX>(zt[q][c], Z, ldz, n, nev, p0 + 16 * q + rsub,
-                                col_base + 16 * c, inside);
+                                col_base + 16 * c, inside, pred_global);
         }
 #pragma unroll
         for (int c = 0; c < D; ++c) load_chunk<CPLX, D>(ops, 0, c, lane, ring_re, ring_im, c);
@@ -824,7 +891,7 @@ __device__ __attribute__((always_inline)) inline void blocked_strip(int64_t n, i
 #pragma unroll
                 for (int c = 0; c < CT; ++c)
                     load_tile<CPLX>(znext[c], Z, ldz, n, nev, p0 - 16 + rsub, col_base + 16 * c,
-                                    inside);
+                                    inside, pred_global);
             }
 
             // operand chunk c of this block sits in ring slot c % D; as soon
@@ -866,7 +933,7 @@ __device__ __attribute__((always_inline)) inline void blocked_strip(int64_t n, i
 #pragma unroll
                     for (int cc = 0; cc < CT; ++cc)
                         store_tile<CPLX>(zb[cc], Z, ldz, n, nev, rb + rsub, col_base + 16 * cc,
-                                         inside);
+                                         inside, coh_out);
                 }
             };
 
@@ -1015,10 +1082,10 @@ __device__ __attribute__((always_inline)) inline void blocked_strip(int64_t n, i
                     for (int c = 0; c < CT; ++c) {
                         if constexpr (CPLX)
                             store_tile<CPLX>(zt[h][c], Z, ldz, n, nev, p0 + 16 * q + rsub,
-                                             col_base + 16 * c);
+                                             col_base + 16 * c, false, coh_out);
                         else
                             store_tile<CPLX>(zsh[h + 1][c], Z, ldz, n, nev, p0 + 16 * h + rsub,
-                                             col_base + 16 * c);
+                                             col_base + 16 * c, false, coh_out);
                     }
                 }
             }
@@ -1027,9 +1094,8 @@ __device__ __attribute__((always_inline)) inline void blocked_strip(int64_t n, i
                                    __HIP_MEMORY_SCOPE_WORKGROUP);
             __hip_atomic_store(&prog[w], (int)(j * (nblk + 1) + t + 1), __ATOMIC_RELEASE,
                                __HIP_MEMORY_SCOPE_WORKGROUP);
-            if (ngroups > 1 && w == NW - 1)   // the next group's wave 0 waits on this
-                __hip_atomic_store(&gprog[grp], (int)(j * (nblk + 1) + t + 1), __ATOMIC_RELEASE,
-                                   __HIP_MEMORY_SCOPE_AGENT);
+            if (coh_out)   // the next group's wave 0 waits on this
+                publish_global(&gprog[grp], (int)(j * (nblk + 1) + t + 1));
             if constexpr (CPLX) {
                 rot = ret;
             } else if (has_next) {
