@@ -162,13 +162,42 @@ __device__ inline cx shfl_x(cx v, int src)
     return r;
 }
 
-// sums over the 64 lanes of N values at once (every lane gets every sum);
-// the butterflies of the N values are independent and interleave
+// x from another lane of the same 16-lane row, by a DPP move of each 32-bit
+// half (a VALU operation: no trip through the LDS crossbar)
+template <int CTRL>
+__device__ inline double dpp_f64(double x)
+{
+    const uint64_t u = __builtin_bit_cast(uint64_t, x);
+    const int lo = __builtin_amdgcn_update_dpp(0, (int)(uint32_t)u, CTRL, 0xF, 0xF, false);
+    const int hi = __builtin_amdgcn_update_dpp(0, (int)(uint32_t)(u >> 32), CTRL, 0xF, 0xF, false);
+    return __builtin_bit_cast(double, ((uint64_t)(uint32_t)hi << 32) | (uint32_t)lo);
+}
+
+// sum over a 16-lane row, in every lane of the row: pairs within quads, then
+// quads within half rows, then half rows (quad_perm [1,0,3,2], [2,3,0,1],
+// row_half_mirror, row_mirror)
+__device__ inline double row_sum(double x)
+{
+    x += dpp_f64<0xB1>(x);
+    x += dpp_f64<0x4E>(x);
+    x += dpp_f64<0x141>(x);
+    x += dpp_f64<0x140>(x);
+    return x;
+}
+
+// sums over the 64 lanes of N values at once (every lane gets every sum):
+// within rows by DPP, then across the four rows by two lane swaps; the N
+// values are independent and interleave
 template <bool C, int N>
 __device__ inline void wave_sums(cx (&v)[N])
 {
 #pragma unroll
-    for (int off = 32; off >= 1; off >>= 1) {
+    for (int t = 0; t < N; ++t) {
+        v[t].re = row_sum(v[t].re);
+        if constexpr (C) v[t].im = row_sum(v[t].im);
+    }
+#pragma unroll
+    for (int off = 16; off <= 32; off <<= 1) {
 #pragma unroll
         for (int t = 0; t < N; ++t) {
             v[t].re += __shfl_xor(v[t].re, off, 64);
@@ -179,8 +208,9 @@ __device__ inline void wave_sums(cx (&v)[N])
 
 __device__ inline double wave_sum1(double x)
 {
-#pragma unroll
-    for (int off = 32; off >= 1; off >>= 1) x += __shfl_xor(x, off, 64);
+    x = row_sum(x);
+    x += __shfl_xor(x, 16, 64);
+    x += __shfl_xor(x, 32, 64);
     return x;
 }
 
@@ -309,19 +339,6 @@ __global__ __launch_bounds__(64 * NW) void k_chase(int64_t n, int b,
                 yr[t] = ldx_coh<C>(okr ? at(r0 + len + lane, r0 + m) : bd);
                 ad[t] = ldx_coh<C>(okd ? at(r0 + lane, r0 + m) : bd);
             }
-#pragma unroll
-            for (int t = 0; t < COLS; ++t) {
-                const int m = w + NW * t;
-                const bool okr = m < len && lane < nr && !(crow && m == b - 1);
-                const bool okd = m < len && lane >= m && lane < len;
-                if (!okr) yr[t] = cx{0.0, 0.0};
-                if (!okd) ad[t] = cx{0.0, 0.0};
-                if (okd) {
-                    stx<C>(&As[(m * CH_PITCH + lane) * E], ad[t]);
-                    if (lane > m) stx<C>(&As[(lane * CH_PITCH + m) * E], cx{ad[t].re, -ad[t].im});
-                }
-            }
-
             // 2. the reflector (wave 0)
             if (w == 0) {
                 const double ar = __shfl(x.re, 0, 64);
@@ -357,6 +374,21 @@ __global__ __launch_bounds__(64 * NW) void k_chase(int64_t n, int b,
                 if (lane < b) stx<C>(hv + (kref * b + lane) * E, v);
                 if (lane < len) stx_coh<C>(at(r0 + lane, c), lane == 0 ? cx{beta, 0.0} : cx{0.0, 0.0});
             }
+            // the mirror of the diagonal block (its loads have been in flight
+            // while wave 0 built the reflector)
+#pragma unroll
+            for (int t = 0; t < COLS; ++t) {
+                const int m = w + NW * t;
+                const bool okr = m < len && lane < nr && !(crow && m == b - 1);
+                const bool okd = m < len && lane >= m && lane < len;
+                if (!okr) yr[t] = cx{0.0, 0.0};
+                if (!okd) ad[t] = cx{0.0, 0.0};
+                if (okd) {
+                    stx<C>(&As[(m * CH_PITCH + lane) * E], ad[t]);
+                    if (lane > m) stx<C>(&As[(lane * CH_PITCH + m) * E], cx{ad[t].re, -ad[t].im});
+                }
+            }
+
             __syncthreads();
 
             // 3. left block; partial products of the right and diagonal blocks
