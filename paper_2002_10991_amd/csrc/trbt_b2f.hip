@@ -367,11 +367,11 @@ __global__ __launch_bounds__(64 * NW) void k_b2f_apply(
             }
             auto v_upd = [&](int kk) -> Elt<CPLX> {
                 if constexpr (HOIST) return vu[kk];
-                else return v_at<CPLX>(V, ldv, n, nbw, J, r0 + i16, jp + 4 * kk + g4);
+                else return v_sel<CPLX>(V, ldv, n, nbw, J, r0 + i16, jp + 4 * kk + g4);
             };
             auto v_acc = [&](int u, int a) -> Elt<CPLX> {
                 if constexpr (HOIST) return va[u][a];
-                else return v_at<CPLX>(V, ldv, n, nbw, J, r0 + 4 * u + g4, jn + 16 * a + i16);
+                else return v_sel<CPLX>(V, ldv, n, nbw, J, r0 + 4 * u + g4, jn + 16 * a + i16);
             };
             if (in_p) {
                 // Z -= V_p W'_p: A[i][k] = V[r0+i][jp+k0+k], B = W'_p rows k0..k0+3
