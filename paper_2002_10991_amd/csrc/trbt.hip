@@ -48,11 +48,21 @@ inline int device_cus()
     return cus;
 }
 
+// Window form of the single-problem kernels: complex windows always rotate;
+// real ones rotate for nbw <= 64, where each wave takes two column tiles
+// (twice the MFMA work per operand chunk, and the rotation saves the
+// registers of the slide), and stay fixed for the wider bands (one tile).
+template <int NB, bool CPLX>
+constexpr bool rotating_window()
+{
+    return CPLX || NB <= 64;
+}
+
 // Launch the blocked forward kernel, with slot groups when the strips alone
 // leave CUs idle and the grid fits on the device at once (a cooperative
 // launch guarantees the workgroups of a strip run concurrently); otherwise
 // one workgroup per strip.
-template <int NB, int CT, bool CPLX, int D, int NW>
+template <int NB, int CT, bool CPLX, int D, int NW, bool ROT>
 int launch_blocked(int64_t n, int64_t nev, const double* ws, double* Z, int64_t ldz,
                    unsigned* err, int* gprog, hipStream_t st)
 {
@@ -65,7 +75,7 @@ int launch_blocked(int64_t n, int64_t nev, const double* ws, double* Z, int64_t 
         if (G > rounds) G = rounds;
         if (G > GMAX) G = GMAX;
     }
-    auto kern = k_blocked<NB, CT, CPLX, D, NW>;
+    auto kern = k_blocked<NB, CT, CPLX, D, NW, ROT>;
     if (G > 1) {
         const int64_t grid = (strips + 7) / 8 * 8 * G;
         int per_cu = 0;
@@ -108,8 +118,9 @@ int prepare(int64_t n, int nbw, const double* hv, const double* ht, void* work,
     hipLaunchKernelGGL(k_zero_words, dim3(1), dim3(64), 0, st, (unsigned*)work, 64);
 #define TRBT_PACK(NBV)                                                                         \
     case NBV:                                                                                  \
-        hipLaunchKernelGGL((k_pack<NBV, CPLX>), dim3((unsigned)nblocks), dim3(256), 0, st, n, \
-                           hv, ht, ws + HDR_BYTES / sizeof(double));                           \
+        hipLaunchKernelGGL((k_pack<NBV, CPLX, rotating_window<NBV, CPLX>()>),                  \
+                           dim3((unsigned)nblocks), dim3(256), 0, st, n, hv, ht,               \
+                           ws + HDR_BYTES / sizeof(double));                                   \
         break;
     switch (nbw) {
         TRBT_PACK(16)
@@ -143,12 +154,16 @@ int apply(int64_t n, int nbw, int64_t nev, const double* hv, const double* ht, d
         unsigned* err = (unsigned*)work;
         int* gprog = (int*)((char*)work + blocked_bytes(n, nbw, CPLX));
         // nbw > 64: windows of 6..9 tiles need one wave per SIMD (4 waves,
-        // all 512 registers) and a half-block operand ring
+        // all 512 registers) and a half-block operand ring; real nbw <= 64:
+        // two column tiles per wave on a rotating window
 #define TRBT_MAIN(NBV)                                                                         \
     case NBV: {                                                                                \
+        constexpr bool ROT = rotating_window<NBV, CPLX>();                                     \
+        constexpr int CTV = (!CPLX && ROT) ? 2 : 1;                                            \
         constexpr int NW = NBV <= 64 ? WAVES : 4;                                              \
-        constexpr int D = (NBV <= 64 || CPLX) ? ring_depth<NBV, CPLX>() : 4 * (NBV / 16 + 1);  \
-        return launch_blocked<NBV, 1, CPLX, D, NW>(n, nev, ws, Z, ldz, err, gprog, st);        \
+        constexpr int D = (NBV <= 64 || CPLX) ? ring_depth<NBV, CPLX, CTV>()                   \
+                                              : 4 * (NBV / 16 + 1);                            \
+        return launch_blocked<NBV, CTV, CPLX, D, NW, ROT>(n, nev, ws, Z, ldz, err, gprog, st); \
     }
         switch (nbw) {
             TRBT_MAIN(16)

@@ -201,12 +201,15 @@ struct Geo {
 // g, g+4, g+8, g+12 of column j), chunk (q, u) of window tile q:
 //   A1 chunk lane l: A1[l%16][16q + 4u + l/16]     stored at position 4h+u
 //   -V chunk lane l: -Vt[16q + l%16][4u + l/16]    stored at position
-//                    4NT + u*NT + (NT-1-h) (real), 4NT + 4(NT-1-h) + u (complex)
+//                    4NT + u*NT + (NT-1-h) (fixed window),
+//                    4NT + 4(NT-1-h) + u (rotating window)
 // where h is the register tile that holds window tile q during this block:
-// h = q for real blocks; for complex blocks h = (q + rot) mod NT, the main
-// kernel never moving a tile between registers (the window's top tile sits
-// in register tile rot = (-o) mod NT in the o-th block of a slot).  So the
-// chunks are stored in exactly the order the main kernel consumes them.
+// h = q for a fixed window (the real kernels with one column tile);
+// h = (q + rot) mod NT for a rotating window (complex, and real with two
+// column tiles per wave), the main kernel never moving a tile between
+// registers (the window's top tile sits in register tile rot = (-o) mod NT
+// in the o-th block of a slot).  So the chunks are stored in exactly the
+// order the main kernel consumes them.
 // --------------------------------------------------------------------------
 // Shared-memory image of one block's compact-WY factor (see above).
 template <int NB, bool CPLX>
@@ -357,7 +360,7 @@ __device__ inline void wy_factor(int64_t n, const double* __restrict__ hv,
 // pack_block packs block `blk` (slot-major numbering) of one problem into
 // ws (the problem's packed-block array); all 256 threads of the workgroup
 // take part.
-template <int NB, bool CPLX>
+template <int NB, bool CPLX, bool ROT = CPLX>
 __device__ inline void pack_block(int64_t n, const double* __restrict__ hv,
                                   const double* __restrict__ ht, double* __restrict__ ws,
                                   int64_t blk)
@@ -371,7 +374,7 @@ __device__ inline void pack_block(int64_t n, const double* __restrict__ hv,
     const int tid = threadIdx.x;
     // register tile of window tile 0 in this block (the block's position in
     // its slot's sequence is W.t - W.j * NB/16); real windows do not rotate
-    const int rot = CPLX ? (int)((NT - (W.t - W.j * (NB / 16)) % NT) % NT) : 0;
+    const int rot = ROT ? (int)((NT - (W.t - W.j * (NB / 16)) % NT) % NT) : 0;
     double* out = ws + (size_t)blk * G::PB;
     {   // A1 = T V^H, as A1^T = conj(V) T^T on MFMA, one 16-row window tile
         // q per product (K = the 16 reflectors), wave w taking q = w (mod 4).
@@ -409,19 +412,19 @@ __device__ inline void pack_block(int64_t n, const double* __restrict__ hv,
             // window up.  Complex: tile by tile from the bottom up, u
             // ascending inside a tile.
             const int r = 16 * q + lane % 16, p = 4 * u + lane / 16;
-            const int pos = CPLX ? (NT - 1 - h) * 4 + u : u * NT + (NT - 1 - h);
+            const int pos = ROT ? (NT - 1 - h) * 4 + u : u * NT + (NT - 1 - h);
             out[G::A1_DBL + pos * G::CHUNK + lane] = -Vt[r][p][0];
             if (CPLX) out[G::A1_DBL + pos * G::CHUNK + 64 + lane] = -Vt[r][p][NC - 1];
         }
     }
 }
 
-template <int NB, bool CPLX>
+template <int NB, bool CPLX, bool ROT = CPLX>
 __global__ __launch_bounds__(256) void k_pack(int64_t n, const double* __restrict__ hv,
                                               const double* __restrict__ ht,
                                               double* __restrict__ ws)
 {
-    pack_block<NB, CPLX>(n, hv, ht, ws, blockIdx.x);
+    pack_block<NB, CPLX, ROT>(n, hv, ht, ws, blockIdx.x);
 }
 
 // --------------------------------------------------------------------------
@@ -806,7 +809,7 @@ __device__ inline void lds_get(Tile<CPLX> (&t)[CT], const double* __restrict__ s
 //   ckpt[((((b * NT + q) * nstrips + strip) * NC + plane) * 4 + e) * 64 + lane]
 // b = the block's slot-major index, q = tile of the window, plane = real or
 // imaginary part (NC = 2 complex, 1 real), e = element.
-template <int NB, int CT, bool CPLX, int D, int NW, bool CKPT = false>
+template <int NB, int CT, bool CPLX, int D, int NW, bool CKPT = false, bool ROT = CPLX>
 __device__ __attribute__((always_inline)) inline void blocked_strip(int64_t n, int64_t nev, const double* __restrict__ wsb,
                                      double* __restrict__ Z, int64_t ldz,
                                      unsigned* __restrict__ err, int64_t strip,
@@ -821,6 +824,8 @@ __device__ __attribute__((always_inline)) inline void blocked_strip(int64_t n, i
     // last values read from the counters this wave waits on (all only grow)
     int seen_prog = 0, seen_written = 0, seen_consumed = 0;
     static_assert(!CKPT || CT == 1, "checkpoints: one 16-column tile");
+    static_assert(ROT || !CPLX, "complex windows rotate");
+    static_assert(!CKPT || ROT == CPLX, "checkpoints: the default window of the element type");
     using G = Geo<NB, CPLX>;
     constexpr int NT = G::NT;
     constexpr int NCH = 8 * NT;            // operand chunks per block
@@ -908,7 +913,7 @@ __device__ __attribute__((always_inline)) inline void blocked_strip(int64_t n, i
                                         ring_re, ring_im, slot);
             };
             bool xfail = false;
-            Tile<CPLX> zsh[CPLX ? 1 : NT + 1][CT];   // real: the window after the slide
+            Tile<CPLX> zsh[ROT ? 1 : NT + 1][CT];   // fixed window: the window after the slide
             auto store_bottom = [&](const Tile<CPLX> (&zb)[CT]) {   // the final bottom tile
                 if (!has_next) return;
                 // to wave w+1 through LDS: slot j+1 exists, is in this round, and
@@ -937,7 +942,37 @@ __device__ __attribute__((always_inline)) inline void blocked_strip(int64_t n, i
                 }
             };
 
-            if constexpr (CPLX) {
+            if constexpr (ROT && !CPLX) {
+                // Real, rotating window (two column tiles): GEMM1 by
+                // register tile, then GEMM2 register tiles from NT-1 down,
+                // u ascending; each operand chunk feeds CT MFMAs.
+                Tile<CPLX> y[2][CT];
+#pragma unroll
+                for (int hp = 0; hp < 2; ++hp)
+#pragma unroll
+                    for (int cc = 0; cc < CT; ++cc) y[hp][cc].re = d4{0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+                for (int c = 0; c < 4 * NT; ++c) {
+                    const double ar = ring_re[c % D];
+                    refill(c);
+                    const int h = c / 4, u = c % 4;
+#pragma unroll
+                    for (int cc = 0; cc < CT; ++cc)
+                        y[h & 1][cc].re = mfma_n<0>(ar, zt[h][cc].re[u], y[h & 1][cc].re);
+                }
+#pragma unroll
+                for (int cc = 0; cc < CT; ++cc) y[0][cc].re += y[1][cc].re;
+#pragma unroll
+                for (int c2 = 0; c2 < 4 * NT; ++c2) {
+                    const int c = 4 * NT + c2;
+                    const double ar = ring_re[c % D];
+                    refill(c);
+                    const int h = NT - 1 - c2 / 4, u = c2 % 4;
+#pragma unroll
+                    for (int cc = 0; cc < CT; ++cc)
+                        zt[h][cc].re = mfma_n<0>(ar, y[0][cc].re[u], zt[h][cc].re);
+                }
+            } else if constexpr (CPLX) {
                 // Complex products with three real MFMAs each.
                 // GEMM1 (Gauss): Y = A1 * Zwin from P1 = sum ax, P2 = sum by and
                 // P3 = sum (a+b)(x+y), (a + ib)(x + iy) = (P1 - P2) + i(P3 - P1 - P2).
@@ -1059,7 +1094,7 @@ __device__ __attribute__((always_inline)) inline void blocked_strip(int64_t n, i
                 }
             }
 
-            if constexpr (CPLX) {
+            if constexpr (ROT) {
                 // the bottom tile is final: hand it off; its registers take
                 // the next block's top tile
 #pragma unroll
@@ -1080,7 +1115,7 @@ __device__ __attribute__((always_inline)) inline void blocked_strip(int64_t n, i
                     const int q = h >= rot ? h - rot : h + NT - rot;
 #pragma unroll
                     for (int c = 0; c < CT; ++c) {
-                        if constexpr (CPLX)
+                        if constexpr (ROT)
                             store_tile<CPLX>(zt[h][c], Z, ldz, n, nev, p0 + 16 * q + rsub,
                                              col_base + 16 * c, false, coh_out);
                         else
@@ -1096,7 +1131,7 @@ __device__ __attribute__((always_inline)) inline void blocked_strip(int64_t n, i
                                __HIP_MEMORY_SCOPE_WORKGROUP);
             if (coh_out)   // the next group's wave 0 waits on this
                 publish_global(&gprog[grp], (int)(j * (nblk + 1) + t + 1));
-            if constexpr (CPLX) {
+            if constexpr (ROT) {
                 rot = ret;
             } else if (has_next) {
 #pragma unroll
@@ -1116,7 +1151,7 @@ __device__ __attribute__((always_inline)) inline void blocked_strip(int64_t n, i
 // ((b / 8) / G) * 8 + b % 8, group (b / 8) % G; the grid is padded to a
 // multiple of 8 strips and the workgroups of padding strips leave at once.
 // gprog: G progress counters per strip (zero on entry).
-template <int NB, int CT, bool CPLX, int D, int NW>
+template <int NB, int CT, bool CPLX, int D, int NW, bool ROT = CPLX>
 __global__ __launch_bounds__(64 * NW) void k_blocked(int64_t n, int64_t nev,
                                                      const double* __restrict__ ws,
                                                      double* __restrict__ Z, int64_t ldz,
@@ -1134,9 +1169,9 @@ __global__ __launch_bounds__(64 * NW) void k_blocked(int64_t n, int64_t nev,
     }
     S.reset();
     __syncthreads();
-    blocked_strip<NB, CT, CPLX, D, NW>(n, nev, ws + HDR_BYTES / sizeof(double), Z, ldz, err,
-                                       strip, S, nullptr, 0, G, g,
-                                       G > 1 ? gprog + strip * G : nullptr);
+    blocked_strip<NB, CT, CPLX, D, NW, false, ROT>(n, nev, ws + HDR_BYTES / sizeof(double), Z,
+                                                   ldz, err, strip, S, nullptr, 0, G, g,
+                                                   G > 1 ? gprog + strip * G : nullptr);
 }
 
 __global__ void k_zero_words(unsigned* p, int count)
