@@ -714,6 +714,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-shapes", action="store_true",
                     help="skip the other single-problem shapes (C1, C2, C3s, C3w)")
+    ap.add_argument("--shapes-only", action="store_true",
+                    help="only the other single-problem shapes")
     ap.add_argument("--no-batched", action="store_true",
                     help="skip the batched-vs-looped comparison on the 64-problem workload")
     ap.add_argument("--batched-only", action="store_true",
@@ -774,6 +776,9 @@ def main():
     if args.b2f_only:
         print(json.dumps({"band_to_full": b2f_leg(args.steps, args.warmup,
                                                   not args.no_cpu_baseline)}), flush=True)
+        return
+    if args.shapes_only:
+        print(json.dumps({"shapes": shapes_leg(args.steps, args.warmup)}), flush=True)
         return
     if args.adjoint_only:
         print(json.dumps({"adjoint_vs_plain": adjoint_leg(args.warmup, not args.no_plain),

@@ -75,8 +75,8 @@ int launch_blocked(int64_t n, int64_t nev, const double* ws, double* Z, int64_t 
         if (G > rounds) G = rounds;
         if (G > GMAX) G = GMAX;
     }
-    auto kern = k_blocked<NB, CT, CPLX, D, NW, ROT>;
     if (G > 1) {
+        auto kern = k_blocked<NB, CT, CPLX, D, NW, ROT, true>;
         const int64_t grid = (strips + 7) / 8 * 8 * G;
         int per_cu = 0;
         if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kern, 64 * NW, 0) ==
@@ -93,8 +93,8 @@ int launch_blocked(int64_t n, int64_t nev, const double* ws, double* Z, int64_t 
         }
         (void)hipGetLastError();   // fall back to one workgroup per strip
     }
-    hipLaunchKernelGGL(kern, dim3((unsigned)strips), dim3(64 * NW), 0, st, n, nev, ws, Z, ldz,
-                       err, 1, (int*)nullptr);
+    hipLaunchKernelGGL((k_blocked<NB, CT, CPLX, D, NW, ROT, false>), dim3((unsigned)strips),
+                       dim3(64 * NW), 0, st, n, nev, ws, Z, ldz, err, 1, (int*)nullptr);
     return hipGetLastError() == hipSuccess ? TRBT_SUCCESS : TRBT_ERR_HIP;
 }
 template <bool CPLX>

@@ -209,7 +209,7 @@ __global__ __launch_bounds__(64 * NW) void k_blocked_ckpt(int64_t n, int64_t nev
     __shared__ StripLds<NB, 1, CPLX, NW> S;
     S.reset();
     __syncthreads();
-    blocked_strip<NB, 1, CPLX, ring_depth<NB, CPLX>(), NW, true>(
+    blocked_strip<NB, 1, CPLX, ring_depth<NB, CPLX>(), NW, true, true>(
         n, nev, blocks, Z, ldz, err, blockIdx.x, S, ckpt, gridDim.x);
 }
 
@@ -428,7 +428,7 @@ __global__ __launch_bounds__(64 * NW) void k_adj_fwd_sweep(int64_t n, int64_t ne
     if ((int64_t)blockIdx.x < ns) {
         U.f.reset();
         __syncthreads();
-        blocked_strip<NB, 1, CPLX, ring_depth<NB, CPLX>(), NW, true>(
+        blocked_strip<NB, 1, CPLX, ring_depth<NB, CPLX>(), NW, true, true>(
             n, nev, blocks, Z, ldz, err, blockIdx.x, U.f, ckpt, ns);
     } else {
         U.b.reset();
@@ -1051,7 +1051,7 @@ void blocked_forward(int64_t n, int64_t nev, const double* hv, const double* ht,
 {
     double* fwd = (double*)(ws + L.fwd);
     const unsigned nb = (unsigned)L.nblocks, ns = (unsigned)L.nstrips;
-    hipLaunchKernelGGL((k_pack<NB, false>), dim3(nb), dim3(256), 0, st, n, hv, ht, fwd);
+    hipLaunchKernelGGL((k_pack<NB, false, true>), dim3(nb), dim3(256), 0, st, n, hv, ht, fwd);
     hipLaunchKernelGGL((k_blocked_ckpt<NB, ADJ_WAVES, false>), dim3(ns), dim3(64 * ADJ_WAVES), 0,
                        st, n, nev, (const double*)fwd, Z, ldz, (double*)(ws + L.ckpt),
                        (unsigned*)ws);
@@ -1086,7 +1086,7 @@ void blocked_both(int64_t n, int64_t nev, const double* hv, const double* ht, do
     double* apk = (double*)(ws + L.apk);
     double* gck = (double*)(ws + L.gck);
     const unsigned nb = (unsigned)L.nblocks, ns = (unsigned)L.nstrips;
-    hipLaunchKernelGGL((k_pack<NB, CPLX>), dim3(nb), dim3(256), 0, st, n, hv, ht, fwd);
+    hipLaunchKernelGGL((k_pack<NB, CPLX, true>), dim3(nb), dim3(256), 0, st, n, hv, ht, fwd);
     hipLaunchKernelGGL((k_pack_adj<NB, CPLX>), dim3(nb), dim3(256), 0, st, n, hv, ht, apk);
     hipLaunchKernelGGL((k_adj_fwd_sweep<NB, NW, CPLX>), dim3(2 * ns), dim3(64 * NW), 0, st, n,
                        nev, (const double*)fwd, Z, ldz, (double*)(ws + L.ckpt),

@@ -809,7 +809,8 @@ __device__ inline void lds_get(Tile<CPLX> (&t)[CT], const double* __restrict__ s
 //   ckpt[((((b * NT + q) * nstrips + strip) * NC + plane) * 4 + e) * 64 + lane]
 // b = the block's slot-major index, q = tile of the window, plane = real or
 // imaginary part (NC = 2 complex, 1 real), e = element.
-template <int NB, int CT, bool CPLX, int D, int NW, bool CKPT = false, bool ROT = CPLX>
+template <int NB, int CT, bool CPLX, int D, int NW, bool CKPT = false, bool ROT = CPLX,
+          bool SG = false>
 __device__ __attribute__((always_inline)) inline void blocked_strip(int64_t n, int64_t nev, const double* __restrict__ wsb,
                                      double* __restrict__ Z, int64_t ldz,
                                      unsigned* __restrict__ err, int64_t strip,
@@ -825,7 +826,6 @@ __device__ __attribute__((always_inline)) inline void blocked_strip(int64_t n, i
     int seen_prog = 0, seen_written = 0, seen_consumed = 0;
     static_assert(!CKPT || CT == 1, "checkpoints: one 16-column tile");
     static_assert(ROT || !CPLX, "complex windows rotate");
-    static_assert(!CKPT || ROT == CPLX, "checkpoints: the default window of the element type");
     using G = Geo<NB, CPLX>;
     constexpr int NT = G::NT;
     constexpr int NCH = 8 * NT;            // operand chunks per block
@@ -846,8 +846,10 @@ __device__ __attribute__((always_inline)) inline void blocked_strip(int64_t n, i
     double ring_re[D], ring_im[D];
     // the predecessor of this wave's slots: wave w-1 of this workgroup, or
     // (wave 0 with slot groups) wave NW-1 of the previous group
-    const bool pred_global = ngroups > 1 && w == 0;
-    const bool coh_out = ngroups > 1 && w == NW - 1;   // this wave's tiles go to another group
+    // (SG: compiled for slot groups; without it the cross-workgroup paths
+    // are not generated at all)
+    const bool pred_global = SG && ngroups > 1 && w == 0;
+    const bool coh_out = SG && ngroups > 1 && w == NW - 1;   // tiles go to another group
     const int* gpred = pred_global ? gprog + (grp + ngroups - 1) % ngroups : nullptr;
     auto wait_pred = [&](int need) -> bool {
         return pred_global ? wait_global(gpred, need, err, lane, seen_prog)
@@ -962,6 +964,20 @@ __device__ __attribute__((always_inline)) inline void blocked_strip(int64_t n, i
                 }
 #pragma unroll
                 for (int cc = 0; cc < CT; ++cc) y[0][cc].re += y[1][cc].re;
+                if constexpr (CKPT) {
+                    // the block's input window (GEMM1 has only read it);
+                    // window tile q sits in register tile (q + rot) mod NT
+                    double* cp = ckpt + ((size_t)(slot_base(j, nblk, nt1) + t - t0) * NT *
+                                             nstrips + strip) * 256 + lane;
+#pragma unroll
+                    for (int h = 0; h < NT; ++h) {
+                        const int q = h >= rot ? h - rot : h + NT - rot;
+#pragma unroll
+                        for (int e = 0; e < 4; ++e)
+                            __builtin_nontemporal_store(
+                                zt[h][0].re[e], &cp[(size_t)q * nstrips * 256 + e * 64]);
+                    }
+                }
 #pragma unroll
                 for (int c2 = 0; c2 < 4 * NT; ++c2) {
                     const int c = 4 * NT + c2;
@@ -1151,7 +1167,7 @@ __device__ __attribute__((always_inline)) inline void blocked_strip(int64_t n, i
 // ((b / 8) / G) * 8 + b % 8, group (b / 8) % G; the grid is padded to a
 // multiple of 8 strips and the workgroups of padding strips leave at once.
 // gprog: G progress counters per strip (zero on entry).
-template <int NB, int CT, bool CPLX, int D, int NW, bool ROT = CPLX>
+template <int NB, int CT, bool CPLX, int D, int NW, bool ROT = CPLX, bool SG = false>
 __global__ __launch_bounds__(64 * NW) void k_blocked(int64_t n, int64_t nev,
                                                      const double* __restrict__ ws,
                                                      double* __restrict__ Z, int64_t ldz,
@@ -1161,7 +1177,7 @@ __global__ __launch_bounds__(64 * NW) void k_blocked(int64_t n, int64_t nev,
     __shared__ StripLds<NB, CT, CPLX, NW> S;
     int64_t strip = blockIdx.x;
     int g = 0;
-    if (G > 1) {
+    if (SG && G > 1) {
         const int64_t i = blockIdx.x / 8;
         strip = (i / G) * 8 + blockIdx.x % 8;
         g = (int)(i % G);
@@ -1169,9 +1185,9 @@ __global__ __launch_bounds__(64 * NW) void k_blocked(int64_t n, int64_t nev,
     }
     S.reset();
     __syncthreads();
-    blocked_strip<NB, CT, CPLX, D, NW, false, ROT>(n, nev, ws + HDR_BYTES / sizeof(double), Z,
-                                                   ldz, err, strip, S, nullptr, 0, G, g,
-                                                   G > 1 ? gprog + strip * G : nullptr);
+    blocked_strip<NB, CT, CPLX, D, NW, false, ROT, SG>(n, nev, ws + HDR_BYTES / sizeof(double),
+                                                       Z, ldz, err, strip, S, nullptr, 0, G, g,
+                                                       SG && G > 1 ? gprog + strip * G : nullptr);
 }
 
 __global__ void k_zero_words(unsigned* p, int count)

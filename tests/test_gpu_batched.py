@@ -163,9 +163,14 @@ def test_empty_and_degenerate_plans(oracle_mod):
 @pytest.mark.parametrize("cfg", [(16, 8, 16), (32, 4, 16), (16, 8, 1)],
                          ids=lambda c: "x".join(map(str, c)))
 def test_batched_equals_looped_bitwise(oracle_mod, cfg):
-    """The batched kernels run the same per-column arithmetic as the single
-    calls (same compact-WY factors, same MFMA sequence per column; strip width
-    and wave count change only the schedule), so results agree bitwise."""
+    """Batched plans against looped single calls.  Where both take the
+    streaming kernel the per-column arithmetic is identical and the results
+    agree bitwise.  Real blocked problems: the single call runs two column
+    tiles per wave on a rotating window, the plan the fixed window -- the
+    same products and compact-WY factors, but the first product's two
+    partial sums group the window tiles differently, so they agree to
+    rounding (the complex forms are the same on both sides and are checked
+    bitwise in test_batched_complex_equals_looped_bitwise)."""
     import paper_2002_10991_amd as T
     torch = _torch()
     shapes = [(300, 32, 150), (97, 32, 33), (200, 16, 17), (150, 48, 65), (129, 24, 31)]
@@ -180,11 +185,11 @@ def test_batched_equals_looped_bitwise(oracle_mod, cfg):
     torch.cuda.synchronize()
     plan.close()
     for i, (n, nbw, nev) in enumerate(shapes):
-        blocked_same = cfg[2] == 16 or nbw not in (16, 32, 48, 64)
-        if blocked_same:
+        both_streaming = nbw not in (16, 32, 48, 64)
+        if both_streaming:
             assert np.array_equal(a.result(i), b.result(i)), (i, shapes[i])
         else:
-            assert _relerr(a.result(i), b.result(i)) <= TOL
+            assert _relerr(a.result(i), b.result(i)) <= 1e-14, (i, shapes[i])
 
 
 def _c4_shapes():
