@@ -199,18 +199,31 @@ __global__ __launch_bounds__(256) void k_pack_adj(int64_t n, const double* __res
 
 // First pass: the forward transformation of a scratch copy of Z_in that
 // also checkpoints every block's input window.
-template <int NB, int NW, bool CPLX>
+// SG: slot groups (G workgroups per strip, numbered like k_blocked's, a
+// cooperative launch; G progress counters per strip in gprog, zero on entry).
+template <int NB, int NW, bool CPLX, bool SG = false>
 __global__ __launch_bounds__(64 * NW) void k_blocked_ckpt(int64_t n, int64_t nev,
                                                           const double* __restrict__ blocks,
                                                           double* __restrict__ Z, int64_t ldz,
                                                           double* __restrict__ ckpt,
-                                                          unsigned* __restrict__ err)
+                                                          unsigned* __restrict__ err, int G = 1,
+                                                          int* __restrict__ gprog = nullptr)
 {
     __shared__ StripLds<NB, 1, CPLX, NW> S;
+    const int64_t nstrips = (nev + 15) / 16;
+    int64_t strip = blockIdx.x;
+    int g = 0;
+    if (SG && G > 1) {
+        const int64_t i = blockIdx.x / 8;
+        strip = (i / G) * 8 + blockIdx.x % 8;
+        g = (int)(i % G);
+        if (strip >= nstrips) return;
+    }
     S.reset();
     __syncthreads();
-    blocked_strip<NB, 1, CPLX, ring_depth<NB, CPLX>(), NW, true, true>(
-        n, nev, blocks, Z, ldz, err, blockIdx.x, S, ckpt, gridDim.x);
+    blocked_strip<NB, 1, CPLX, ring_depth<NB, CPLX>(), NW, true, true, SG>(
+        n, nev, blocks, Z, ldz, err, strip, S, ckpt, nstrips, G, g,
+        SG && G > 1 ? gprog + strip * G : nullptr);
 }
 
 // Lane-to-lane exchange through LDS inside one wave: the wave's LDS
@@ -249,11 +262,11 @@ struct SweepLds {
     }
 };
 
-template <int NB, int NW, bool CPLX>
+template <int NB, int NW, bool CPLX, bool SG = false>
 __device__ __attribute__((always_inline)) inline void adj_sweep_strip(
     int64_t n, int64_t nev, const double* __restrict__ apk, double* __restrict__ G, int64_t ldg,
     double* __restrict__ gck, unsigned* __restrict__ err, int64_t strip, int64_t nstrips,
-    SweepLds<NW, CPLX>& S)
+    SweepLds<NW, CPLX>& S, int ngroups = 1, int grp = 0, int* __restrict__ gprog = nullptr)
 {
     using A = AdjGeo<NB, CPLX>;
     constexpr int NT = A::NT, NC = A::NC, CH = A::CH;
@@ -275,21 +288,32 @@ __device__ __attribute__((always_inline)) inline void adj_sweep_strip(
     // last values read from the counters this wave waits on (all only grow)
     int seen = 0, seen_written = 0, seen_consumed = 0;
     int xput = 0, xget = 0;   // ring tiles put / taken so far
+    // Slot groups, as in blocked_strip: slot j goes to group ((J-1-j)/NW) mod
+    // G, wave (J-1-j) mod NW; wave 0's predecessor (slot j+1) is wave NW-1
+    // of the previous group, which hands its tiles over through G with
+    // device-coherent stores and publishes its progress in gprog.
+    const bool pred_global = SG && ngroups > 1 && w == 0;
+    const bool coh_out = SG && ngroups > 1 && w == NW - 1;
+    const int* gpred = pred_global ? gprog + (grp + ngroups - 1) % ngroups : nullptr;
+    auto wait_pred = [&](int need) -> bool {
+        return pred_global ? wait_global(gpred, need, err, lane, seen)
+                           : wait_counter(prog, wprev, need, err, lane, seen);
+    };
 
     Tile<CPLX> g[NT];
 
-    for (int64_t j = J - 1 - w; j >= 0; j -= NW) {
+    for (int64_t j = J - 1 - ((int64_t)grp * NW + w); j >= 0; j -= (int64_t)NW * ngroups) {
         const int64_t t0 = j * nt1;
         const bool has_succ = j + 1 < J;
         const int64_t t0s = (j + 1) * nt1;
         const int base = (int)((J - 1 - j) * (nblk + 1));    // + nblk - t after block t
         const int base_s = base - (int)(nblk + 1);           // the same for slot j+1
-        if (has_succ && !wait_counter(prog, wprev, base_s + 1, err, lane, seen)) return;
+        if (has_succ && !wait_pred(base_s + 1)) return;
         int64_t p0 = n - 3 - KB * (nblk - 1) - 15 + j * NB;
 #pragma unroll
         for (int q = 0; q < NT; ++q) {
             const bool inside = cols_inside && p0 + 16 * q >= 0 && p0 + 16 * q + 16 <= n;
-            load_tile<CPLX>(g[q], G, ldg, n, nev, p0 + 16 * q + rsub, col, inside);
+            load_tile<CPLX>(g[q], G, ldg, n, nev, p0 + 16 * q + rsub, col, inside, pred_global);
         }
 
         for (int64_t t = nblk - 1; t >= t0; --t, p0 += KB) {
@@ -355,10 +379,11 @@ __device__ __attribute__((always_inline)) inline void adj_sweep_strip(
                                        __HIP_MEMORY_SCOPE_WORKGROUP);
                 } else {
                     store_tile<CPLX>(g[0], G, ldg, n, nev, p0 + rsub, col,
-                                     cols_inside && p0 >= 0 && p0 + 16 <= n);
+                                     cols_inside && p0 >= 0 && p0 + 16 <= n, coh_out);
                 }
                 __hip_atomic_store(&prog[w], base + (int)(nblk - t), __ATOMIC_RELEASE,
                                    __HIP_MEMORY_SCOPE_WORKGROUP);
+                if (coh_out) publish_global(&gprog[grp], base + (int)(nblk - t));
 #pragma unroll
                 for (int q = 0; q + 1 < NT; ++q) g[q] = g[q + 1];
                 if (w > 0 && has_succ && t - 1 > t0s) {   // from wave w-1's ring
@@ -373,36 +398,47 @@ __device__ __attribute__((always_inline)) inline void adj_sweep_strip(
                     __hip_atomic_store(&consumed[w - 1], xget, __ATOMIC_RELEASE,
                                        __HIP_MEMORY_SCOPE_WORKGROUP);
                 } else {
-                    if (has_succ && t - 1 >= t0s &&
-                        !wait_counter(prog, wprev, base_s + (int)(nblk - (t - 1)), err, lane,
-                                      seen))
+                    if (has_succ && t - 1 >= t0s && !wait_pred(base_s + (int)(nblk - (t - 1))))
                         return;
                     const int64_t r = p0 + KB + 16 * (NT - 1);
                     const bool inside = cols_inside && r >= 0 && r + 16 <= n;
-                    load_tile<CPLX>(g[NT - 1], G, ldg, n, nev, r + rsub, col, inside);
+                    load_tile<CPLX>(g[NT - 1], G, ldg, n, nev, r + rsub, col, inside, pred_global);
                 }
             } else {
 #pragma unroll
                 for (int q = 0; q < NT; ++q)
-                    store_tile<CPLX>(g[q], G, ldg, n, nev, p0 + 16 * q + rsub, col);
+                    store_tile<CPLX>(g[q], G, ldg, n, nev, p0 + 16 * q + rsub, col, false,
+                                     coh_out);
                 __hip_atomic_store(&prog[w], base + (int)(nblk - t), __ATOMIC_RELEASE,
                                    __HIP_MEMORY_SCOPE_WORKGROUP);
+                if (coh_out) publish_global(&gprog[grp], base + (int)(nblk - t));
             }
         }
     }
 }
 
-template <int NB, int NW, bool CPLX>
+template <int NB, int NW, bool CPLX, bool SG = false>
 __global__ __launch_bounds__(64 * NW) void k_adj_sweep(int64_t n, int64_t nev,
                                                        const double* __restrict__ apk,
                                                        double* __restrict__ G, int64_t ldg,
                                                        double* __restrict__ gck,
-                                                       unsigned* __restrict__ err)
+                                                       unsigned* __restrict__ err, int NG = 1,
+                                                       int* __restrict__ gprog = nullptr)
 {
     __shared__ SweepLds<NW, CPLX> S;
+    const int64_t nstrips = (nev + 15) / 16;
+    int64_t strip = blockIdx.x;
+    int g = 0;
+    if (SG && NG > 1) {
+        const int64_t i = blockIdx.x / 8;
+        strip = (i / NG) * 8 + blockIdx.x % 8;
+        g = (int)(i % NG);
+        if (strip >= nstrips) return;
+    }
     S.reset();
     __syncthreads();
-    adj_sweep_strip<NB, NW, CPLX>(n, nev, apk, G, ldg, gck, err, blockIdx.x, gridDim.x, S);
+    adj_sweep_strip<NB, NW, CPLX, SG>(n, nev, apk, G, ldg, gck, err, strip, nstrips, S, NG, g,
+                                      SG && NG > 1 ? gprog + strip * NG : nullptr);
 }
 
 // The one-call adjoint runs the checkpointing forward and the sweep in one
@@ -954,8 +990,38 @@ __global__ void k_fill_zero(double* p, int64_t count)
 constexpr int ADJ_WAVES = 8;     // waves (slots in flight) per strip, real
 constexpr int ADJ_WAVES_Z = 4;   // the same, complex (registers: one wave per SIMD)
 
+constexpr int ADJ_GMAX = 4;   // slot groups per strip in the split form, at most
+
+// CUs of the current device (looked up once per device id).
+inline int adj_device_cus()
+{
+    static int cached[64];
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return 0;
+    if (dev >= 0 && dev < 64 && cached[dev]) return cached[dev];
+    int cus = 0;
+    if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
+        return 0;
+    if (dev >= 0 && dev < 64) cached[dev] = cus;
+    return cus;
+}
+
+// Slot groups for a strip kernel of `strips` workgroups with nw waves over
+// J slots: G = min(CUs / strips, rounds of slots, ADJ_GMAX) when the strips
+// alone leave CUs idle, else 1.
+inline int adj_slot_groups(int64_t strips, int64_t J, int nw)
+{
+    const int cus = adj_device_cus();
+    if (cus <= 0 || strips >= cus) return 1;
+    int64_t G = cus / strips;
+    const int64_t rounds = (J + nw - 1) / nw;
+    if (G > rounds) G = rounds;
+    if (G > ADJ_GMAX) G = ADJ_GMAX;
+    return G < 1 ? 1 : (int)G;
+}
+
 struct AdjLayout {
-    size_t zs = 0, fwd = 0, apk = 0, ckpt = 0, gck = 0, part = 0, tape = 0, total = 0;
+    size_t zs = 0, fwd = 0, apk = 0, ckpt = 0, gck = 0, gprog = 0, part = 0, tape = 0, total = 0;
     int64_t nblocks = 0, nstrips = 0, nwaves = 0;
 };
 
@@ -996,6 +1062,8 @@ AdjLayout adj_layout(int64_t n, int nbw, int64_t nev, bool cplx = false)
         off = al(off + (size_t)L.nblocks * nt * L.nstrips * 256 * elt);
         L.gck = off;   // every block's output-gradient window, checkpoint layout
         off = al(off + (size_t)L.nblocks * nt * L.nstrips * 256 * elt);
+        L.gprog = off;   // slot-group progress counters (split form)
+        off = al(off + (size_t)(L.nstrips + 8) * ADJ_GMAX * sizeof(int));
     } else {
         const int64_t nblk = (n - 2 + KB - 1) / KB;
         int64_t ckrows = 0, taperows = 0;
@@ -1042,6 +1110,37 @@ int adj_validate(int64_t n, int nbw, int64_t nev, const double* hv, const double
     return TRBT_SUCCESS;
 }
 
+// Launch a strip kernel of the split form with slot groups when its strips
+// leave CUs idle and the grid fits at once (cooperative launch, zeroed
+// counters), else one workgroup per strip.  kern1 / kernG: the kernel
+// without / with slot groups; args: the kernel's arguments before (G, gprog).
+template <typename K1, typename KG, typename... Args>
+int launch_strips(K1 kern1, KG kernG, int64_t ns, int64_t J, int nw, int* gprog, hipStream_t st,
+                  Args... args)
+{
+    const int G = adj_slot_groups(ns, J, nw);
+    if (G > 1) {
+        const int64_t grid = (ns + 7) / 8 * 8 * G;
+        int per_cu = 0;
+        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kernG, 64 * nw, 0) ==
+                hipSuccess &&
+            (int64_t)per_cu * adj_device_cus() >= grid) {
+            const int cnt = (int)(ns * G);
+            hipLaunchKernelGGL(k_zero_words, dim3((unsigned)((cnt + 255) / 256)), dim3(256), 0, st,
+                               (unsigned*)gprog, cnt);
+            int g32 = G;
+            void* argv[] = {(void*)&args..., (void*)&g32, (void*)&gprog};
+            if (hipLaunchCooperativeKernel(reinterpret_cast<const void*>(kernG),
+                                           dim3((unsigned)grid), dim3(64 * nw), argv, 0,
+                                           st) == hipSuccess)
+                return TRBT_SUCCESS;
+        }
+        (void)hipGetLastError();
+    }
+    hipLaunchKernelGGL(kern1, dim3((unsigned)ns), dim3(64 * nw), 0, st, args..., 1, (int*)nullptr);
+    return hipGetLastError() == hipSuccess ? TRBT_SUCCESS : TRBT_ERR_HIP;
+}
+
 // The adjoint in two halves.  adj_forward: the forward transformation of Z
 // (in place) that also writes the checkpoints into the workspace;
 // adj_backward: the reverse sweep from those checkpoints.
@@ -1050,11 +1149,12 @@ void blocked_forward(int64_t n, int64_t nev, const double* hv, const double* ht,
                      int64_t ldz, char* ws, const AdjLayout& L, hipStream_t st)
 {
     double* fwd = (double*)(ws + L.fwd);
-    const unsigned nb = (unsigned)L.nblocks, ns = (unsigned)L.nstrips;
+    const unsigned nb = (unsigned)L.nblocks;
     hipLaunchKernelGGL((k_pack<NB, false, true>), dim3(nb), dim3(256), 0, st, n, hv, ht, fwd);
-    hipLaunchKernelGGL((k_blocked_ckpt<NB, ADJ_WAVES, false>), dim3(ns), dim3(64 * ADJ_WAVES), 0,
-                       st, n, nev, (const double*)fwd, Z, ldz, (double*)(ws + L.ckpt),
-                       (unsigned*)ws);
+    launch_strips(k_blocked_ckpt<NB, ADJ_WAVES, false, false>,
+                  k_blocked_ckpt<NB, ADJ_WAVES, false, true>, L.nstrips,
+                  sweeps_in_stage(n, NB, 0), ADJ_WAVES, (int*)(ws + L.gprog), st, n, nev,
+                  (const double*)fwd, Z, ldz, (double*)(ws + L.ckpt), (unsigned*)ws);
 }
 
 template <int NB>
@@ -1066,8 +1166,10 @@ void blocked_backward(int64_t n, int64_t nev, const double* hv, const double* ht
     double* gck = (double*)(ws + L.gck);
     const unsigned nb = (unsigned)L.nblocks, ns = (unsigned)L.nstrips;
     hipLaunchKernelGGL((k_pack_adj<NB, false>), dim3(nb), dim3(256), 0, st, n, hv, ht, apk);
-    hipLaunchKernelGGL((k_adj_sweep<NB, ADJ_WAVES, false>), dim3(ns), dim3(64 * ADJ_WAVES), 0, st,
-                       n, nev, (const double*)apk, G, ldg, gck, (unsigned*)ws);
+    launch_strips(k_adj_sweep<NB, ADJ_WAVES, false, false>,
+                  k_adj_sweep<NB, ADJ_WAVES, false, true>, L.nstrips, sweeps_in_stage(n, NB, 0),
+                  ADJ_WAVES, (int*)(ws + L.gprog), st, n, nev, (const double*)apk, G, ldg, gck,
+                  (unsigned*)ws);
     hipLaunchKernelGGL((k_adj_reduce<NB, 4, false>), dim3(nb), dim3(256), 0, st, n, (int64_t)ns,
                        (const double*)apk, (const double*)(ws + L.ckpt), (const double*)gck, dv,
                        dtau);
