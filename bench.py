@@ -753,7 +753,7 @@ def main():
         return
     if args.gpus != 1:
         print(f"bench.py: this build runs on one GPU only; --gpus {args.gpus} is not supported "
-              "(the back-transformation shards by columns with no communication; see DESIGN.md)",
+              "(the back-transformation shards by eigenvector columns with no communication)",
               file=sys.stderr)
         sys.exit(2)
 

@@ -48,16 +48,6 @@ inline int device_cus()
     return cus;
 }
 
-// Window form of the single-problem kernels: complex windows always rotate;
-// real ones rotate for nbw <= 64, where each wave takes two column tiles
-// (twice the MFMA work per operand chunk, and the rotation saves the
-// registers of the slide), and stay fixed for the wider bands (one tile).
-template <int NB, bool CPLX>
-constexpr bool rotating_window()
-{
-    return CPLX || NB <= 64;
-}
-
 // Launch the blocked forward kernel, with slot groups when the strips alone
 // leave CUs idle and the grid fits on the device at once (a cooperative
 // launch guarantees the workgroups of a strip run concurrently); otherwise
@@ -155,11 +145,11 @@ int apply(int64_t n, int nbw, int64_t nev, const double* hv, const double* ht, d
         int* gprog = (int*)((char*)work + blocked_bytes(n, nbw, CPLX));
         // nbw > 64: windows of 6..9 tiles need one wave per SIMD (4 waves,
         // all 512 registers) and a half-block operand ring; real nbw <= 64:
-        // two column tiles per wave on a rotating window
+        // two column tiles per wave
 #define TRBT_MAIN(NBV)                                                                         \
     case NBV: {                                                                                \
         constexpr bool ROT = rotating_window<NBV, CPLX>();                                     \
-        constexpr int CTV = (!CPLX && ROT) ? 2 : 1;                                            \
+        constexpr int CTV = (!CPLX && NBV <= 64) ? 2 : 1;                                       \
         constexpr int NW = NBV <= 64 ? WAVES : 4;                                              \
         constexpr int D = (NBV <= 64 || CPLX) ? ring_depth<NBV, CPLX, CTV>()                   \
                                               : 4 * (NBV / 16 + 1);                            \

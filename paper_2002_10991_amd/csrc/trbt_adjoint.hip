@@ -221,7 +221,8 @@ __global__ __launch_bounds__(64 * NW) void k_blocked_ckpt(int64_t n, int64_t nev
     }
     S.reset();
     __syncthreads();
-    blocked_strip<NB, 1, CPLX, ring_depth<NB, CPLX>(), NW, true, true, SG>(
+    blocked_strip<NB, 1, CPLX, ring_depth<NB, CPLX>(), NW, true, rotating_window<NB, CPLX>(),
+                  SG>(
         n, nev, blocks, Z, ldz, err, strip, S, ckpt, nstrips, G, g,
         SG && G > 1 ? gprog + strip * G : nullptr);
 }
@@ -464,7 +465,8 @@ __global__ __launch_bounds__(64 * NW) void k_adj_fwd_sweep(int64_t n, int64_t ne
     if ((int64_t)blockIdx.x < ns) {
         U.f.reset();
         __syncthreads();
-        blocked_strip<NB, 1, CPLX, ring_depth<NB, CPLX>(), NW, true, true>(
+        blocked_strip<NB, 1, CPLX, ring_depth<NB, CPLX>(), NW, true,
+                      rotating_window<NB, CPLX>()>(
             n, nev, blocks, Z, ldz, err, blockIdx.x, U.f, ckpt, ns);
     } else {
         U.b.reset();
@@ -1150,7 +1152,8 @@ void blocked_forward(int64_t n, int64_t nev, const double* hv, const double* ht,
 {
     double* fwd = (double*)(ws + L.fwd);
     const unsigned nb = (unsigned)L.nblocks;
-    hipLaunchKernelGGL((k_pack<NB, false, true>), dim3(nb), dim3(256), 0, st, n, hv, ht, fwd);
+    hipLaunchKernelGGL((k_pack<NB, false, rotating_window<NB, false>()>), dim3(nb), dim3(256), 0,
+                       st, n, hv, ht, fwd);
     launch_strips(k_blocked_ckpt<NB, ADJ_WAVES, false, false>,
                   k_blocked_ckpt<NB, ADJ_WAVES, false, true>, L.nstrips,
                   sweeps_in_stage(n, NB, 0), ADJ_WAVES, (int*)(ws + L.gprog), st, n, nev,
@@ -1188,7 +1191,8 @@ void blocked_both(int64_t n, int64_t nev, const double* hv, const double* ht, do
     double* apk = (double*)(ws + L.apk);
     double* gck = (double*)(ws + L.gck);
     const unsigned nb = (unsigned)L.nblocks, ns = (unsigned)L.nstrips;
-    hipLaunchKernelGGL((k_pack<NB, CPLX, true>), dim3(nb), dim3(256), 0, st, n, hv, ht, fwd);
+    hipLaunchKernelGGL((k_pack<NB, CPLX, rotating_window<NB, CPLX>()>), dim3(nb), dim3(256), 0,
+                       st, n, hv, ht, fwd);
     hipLaunchKernelGGL((k_pack_adj<NB, CPLX>), dim3(nb), dim3(256), 0, st, n, hv, ht, apk);
     hipLaunchKernelGGL((k_adj_fwd_sweep<NB, NW, CPLX>), dim3(2 * ns), dim3(64 * NW), 0, st, n,
                        nev, (const double*)fwd, Z, ldz, (double*)(ws + L.ckpt),

@@ -91,7 +91,8 @@ __global__ __launch_bounds__(256) void k_pack_batched(const BProb* __restrict__ 
     if (threadIdx.x == 0) s_p = find_problem(probs, nprob, blockIdx.x);
     __syncthreads();
     const BProb& P = probs[s_p];
-    pack_block<NB, CPLX>(P.n, P.hv, P.ht, P.ws, (int64_t)blockIdx.x - P.first);
+    pack_block<NB, CPLX, rotating_window<NB, CPLX>()>(P.n, P.hv, P.ht, P.ws,
+                                                      (int64_t)blockIdx.x - P.first);
 }
 
 // Persistent blocked kernel: one (problem, strip) task at a time per
@@ -128,7 +129,8 @@ __global__ __launch_bounds__(64 * NW) void k_blocked_batched(const BProb* __rest
         if (task < 0) return;
         const BTask tk = tasks[task];
         const BProb& P = probs[tk.prob];
-        blocked_strip<NB, CT, CPLX, D, NW>(P.n, P.nev, P.ws, P.Z, P.ldz, err, tk.strip, S);
+        blocked_strip<NB, CT, CPLX, D, NW, false, rotating_window<NB, CPLX>()>(
+            P.n, P.nev, P.ws, P.Z, P.ldz, err, tk.strip, S);
         __syncthreads();
     }
 }

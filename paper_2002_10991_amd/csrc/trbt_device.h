@@ -357,6 +357,20 @@ __device__ inline void wy_factor(int64_t n, const double* __restrict__ hv,
     __syncthreads();
 }
 
+// Window form of the blocked kernels: complex windows always rotate; real
+// ones rotate for nbw = 48 and 64, where each wave's two column tiles on a
+// fixed window would spill (the slide needs a second set of tile registers),
+// and stay fixed for nbw <= 32 (fewer instructions per block: 5% faster at
+// n = 1024, nbw = 32) and for the wide bands (one tile per wave).  Every
+// form of the back-transformation (single problem, batched, the adjoint's
+// checkpointing forward) takes the same form for the same nbw, so their
+// results agree bitwise.
+template <int NB, bool CPLX>
+constexpr bool rotating_window()
+{
+    return CPLX || (NB > 32 && NB <= 64);
+}
+
 // pack_block packs block `blk` (slot-major numbering) of one problem into
 // ws (the problem's packed-block array); all 256 threads of the workgroup
 // take part.
