@@ -369,7 +369,8 @@ int trbt_band_to_tridi_workspace_bytes(int64_t n, int nbw, int is_complex, size_
  * real symmetric tridiagonal T = diag(d) + subdiag(e) (complex case: e is
  * complex; after the last stage only e[n-2] keeps a nonzero imaginary part),
  * writing the reflectors.
- * Arguments: 1 n >= 0, 2 nbw in [1, 64], 3 ab (device, read-only): B in
+ * Arguments: 1 n in [0, 2^30] (the chase's progress counters are 32-bit;
+ * -1 outside), 2 nbw in [1, 64], 3 ab (device, read-only): B in
  * LAPACK lower band layout, ab[d + k*ldab] = B(k+d, k) for d = 0..nbw
  * (entries with k+d >= n ignored; imaginary parts of the diagonal ignored
  * in the complex case), 4 ldab >= nbw+1, 5 d (device, n reals, out),

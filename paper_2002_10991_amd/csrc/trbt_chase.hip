@@ -274,6 +274,14 @@ __global__ __launch_bounds__(64 * NW) void k_chase(int64_t n, int b,
     __shared__ double tau_s[2];
     __shared__ int64_t s_sh;
     __shared__ int fail_sh;
+    // tail waits of this workgroup that wave 0 has seen end (the other
+    // waves' tail waits read it here instead of polling global memory).  It
+    // only grows over the kernel (every wave counts the same tail waits in
+    // `tick`), so a wave that reads it late still finds a value at least
+    // its own count.
+    __shared__ int64_t seen_sh;
+    if (threadIdx.x == 0) seen_sh = 0;
+    int64_t tick = 0;
 
     auto at = [&](int64_t i, int64_t k) { return bd + ((i - k) + k * LD) * E; };
 
@@ -453,15 +461,36 @@ __global__ __launch_bounds__(64 * NW) void k_chase(int64_t n, int b,
             // tail: (s-1, 0 .. j+2) done (all of stage s-1 when it has no
             // step j+2); with the corner, the last row of the right block:
             // z[b-1] completed with the corner's current value, then that
-            // row's update.  Every step waits, so that a finished (s, j)
+            // row's update.  Every wave waits, so that a finished (s, j)
             // implies a finished (s-1, j+2), and the next step needs no wait
-            // of its own.
+            // of its own.  Wave 0 polls the counter and passes what it saw
+            // to the other waves through LDS; on a failed wait it sets the
+            // error flag and releases them, and the stage runs on without
+            // waiting (its results are discarded: d is filled with NaN).
             if (s > 0) {
-                if (threadIdx.x == 0) {
-                    fail_sh = !chase_wait(&prog[s - 1], (int)(j + 3 < Sp ? j + 3 : Sp), ctl);
+                const int need = (int)(j + 3 < Sp ? j + 3 : Sp);
+                ++tick;
+                if (w == 0) {
+                    if (lane == 0) {
+                        const bool ok = chase_wait(&prog[s - 1], need, ctl);
+                        __hip_atomic_store(&seen_sh, ok ? tick : INT64_MAX, __ATOMIC_RELEASE,
+                                           __HIP_MEMORY_SCOPE_WORKGROUP);
+                    }
+                } else if (__hip_atomic_load(&seen_sh, __ATOMIC_ACQUIRE,
+                                             __HIP_MEMORY_SCOPE_WORKGROUP) < tick) {
+                    // bounded like every wait: on time-out, flag the error
+                    // and go on
+                    const uint64_t t0 = wall_clock64();
+                    while (__hip_atomic_load(&seen_sh, __ATOMIC_ACQUIRE,
+                                             __HIP_MEMORY_SCOPE_WORKGROUP) < tick) {
+                        __builtin_amdgcn_s_sleep(1);
+                        if (wall_clock64() - t0 > CH_WAIT_TICKS) {
+                            __hip_atomic_store(&ctl[1], 1, __ATOMIC_RELAXED,
+                                               __HIP_MEMORY_SCOPE_AGENT);
+                            break;
+                        }
+                    }
                 }
-                __syncthreads();
-                if (fail_sh) return;
             }
             if (corner) {
                 const cx vb = ldx<C>(&vs[(b - 1) * E]);
@@ -489,12 +518,13 @@ __global__ __launch_bounds__(64 * NW) void k_chase(int64_t n, int b,
             for (int t = 0; t < COLS; ++t) car[t] = yr[t];
 
             // publish the step: every wave waits until its (device-coherent)
-            // stores have completed, then one counter store.  A waiting
-            // stage reads the counter, then -- after a barrier -- the band
-            // with device-coherent loads, so it sees every store made
-            // before the counter.  (Agent-scope release and acquire fences
-            // would write back and invalidate the whole L2 of the XCD at
-            // every step.)
+            // stores have completed, the workgroup meets, and one counter
+            // store.  A waiting stage reads the counter, then the band with
+            // device-coherent loads, so it sees every store made before the
+            // counter.  (Agent-scope release and acquire fences would write
+            // back and invalidate the whole L2 of the XCD at every step; one
+            // atomic add per wave instead of the barrier was much slower:
+            // the adds to one address serialise.)
             asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
             __syncthreads();
             if (threadIdx.x == 0)
