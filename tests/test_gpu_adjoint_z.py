@@ -12,6 +12,7 @@ the oracle's per-thread blocks), which moves them by ~1e-15 relative.
 import numpy as np
 import pytest
 
+import oracle_cache
 from conftest import gpu_available
 
 pytestmark = [pytest.mark.gpu,
@@ -144,7 +145,13 @@ def test_complex_adjoint_c5_shape_512_columns(oracle_mod):
     n, nbw, nev = 4096, 64, 512
     Z, G, V, tau = _inputs(n, nbw, nev, 1005)
     gZ, gv, gt = gpu_adjoint_z(Z, G, V, tau, nbw)
-    rZ, rv, rt = oracle_mod.adjoint(Z, G, V, tau, nbw)
+
+    def compute():
+        rZ, rv, rt = oracle_mod.adjoint(Z, G, V, tau, nbw)
+        return {"dZ": rZ, "dv": rv, "dtau": rt}
+    r = oracle_cache.cached("adjoint", dict(n=n, nbw=nbw, nev=nev, dtype="z", seed=1005),
+                            compute)
+    rZ, rv, rt = r["dZ"], r["dv"], r["dtau"]
     e = (_relerr(gZ, rZ), _relerr(gv, rv), _relerr(gt, rt))
     print(f"[gpu] complex adjoint nev=512 rel errors {e}", flush=True)
     assert max(e) <= TOL

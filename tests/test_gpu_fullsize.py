@@ -9,6 +9,7 @@ eigenvectors of T) is in test_gpu_workloads.py."""
 import numpy as np
 import pytest
 
+import oracle_cache
 from conftest import gpu_available
 
 pytestmark = [pytest.mark.gpu,
@@ -39,9 +40,11 @@ def _run_prepare_apply(n, nbw, nev, V, tau, Z):
     return Zbuf
 
 
-def _sampled_check(oracle_mod, Zbuf, Z, V, tau, nbw, cols):
+def _sampled_check(oracle_mod, Zbuf, Z, V, tau, nbw, cols, key):
     out = Zbuf[cols].cpu().numpy().T
-    ref = oracle_mod.back_transform(Z[:, cols], V, tau, nbw)
+    ref = oracle_cache.cached(
+        "back_transform_cols", dict(key, nbw=nbw, cols=cols),
+        lambda: {"ref": oracle_mod.back_transform(Z[:, cols], V, tau, nbw)})["ref"]
     err = np.linalg.norm(out - ref) / np.linalg.norm(ref)
     print(f"[gpu] {len(cols)} sampled columns: rel err {err:.2e}", flush=True)
     assert err <= TOL
@@ -74,7 +77,7 @@ def test_full_size_sampled_columns(oracle_mod, cfg):
     pick = np.random.default_rng(7).choice(rest, want - len(edge), replace=False)
     cols = np.unique(np.concatenate([edge, pick]))
     assert len(cols) == want
-    _sampled_check(oracle_mod, Zbuf, Z, V, tau, nbw, cols)
+    _sampled_check(oracle_mod, Zbuf, Z, V, tau, nbw, cols, dict(cfg=cfg, **c))
 
 
 @pytest.mark.parametrize("dtype", ["d", "z"])
@@ -82,11 +85,18 @@ def test_chase_reflectors_n2048_nbw64(oracle_mod, dtype):
     import synth
     n, nbw, nev = 2048, 64, 300
     ab = synth.band_matrix(n, nbw, 4242, dtype, diag_shift=True)
-    r = oracle_mod.band_to_tridiagonal(ab, nbw)
     Z = synth.gaussian(n, nev, 4243, dtype)
+
+    def compute():
+        r = oracle_mod.band_to_tridiagonal(ab, nbw)
+        return {"hh_v": r["hh_v"], "hh_tau": r["hh_tau"],
+                "ref": oracle_mod.back_transform(Z, r["hh_v"], r["hh_tau"], nbw)}
+    r = oracle_cache.cached("chase_then_back_transform",
+                            dict(n=n, nbw=nbw, nev=nev, dtype=dtype, band_seed=4242,
+                                 diag_shift=True, z_seed=4243), compute)
     Zbuf = _run_prepare_apply(n, nbw, nev, r["hh_v"], r["hh_tau"], Z)
     out = Zbuf.cpu().numpy().T
-    ref = oracle_mod.back_transform(Z, r["hh_v"], r["hh_tau"], nbw)
+    ref = r["ref"]
     assert np.linalg.norm(out - ref) / np.linalg.norm(ref) <= TOL
 
 
