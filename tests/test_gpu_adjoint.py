@@ -300,7 +300,35 @@ def test_c5_full_size_properties(oracle_mod):
     assert abs(fd - an) <= 1e-6 * max(abs(an), 1.0), (fd, an)
 
 
-@pytest.mark.parametrize("n,nbw,nev", [(301, 64, 63), (150, 32, 40), (90, 8, 31), (100, 24, 17)])
+def _split_adjoint(Z, G, V, tau, nbw):
+    """The split pair on device copies: returns (forward result, dL/dZ_in,
+    dv, dtau, fault word)."""
+    import paper_2002_10991_amd as T
+    torch = _torch()
+    n, nev = Z.shape
+    Vd = torch.from_numpy(V).to("cuda")
+    td = torch.from_numpy(tau).to("cuda")
+    zb = torch.from_numpy(np.ascontiguousarray(Z.T)).to("cuda")
+    gb = torch.from_numpy(np.ascontiguousarray(G.T)).to("cuda")
+    K = len(tau)
+    dv = torch.empty(K, nbw, dtype=torch.float64, device="cuda")
+    dt = torch.empty(K, dtype=torch.float64, device="cuda")
+    nb = T.trbt_adjoint_workspace_bytes_d(n, nbw, nev)
+    w = torch.empty(nb + 256, dtype=torch.uint8, device="cuda")
+    w = w[(-w.data_ptr()) % 256:][:nb]
+    assert T.trans_ev_tridi_to_band_fwd_ckpt_d(n, nbw, nev, Vd, td, zb, n, 16, w, nb) == 0
+    assert T.trans_ev_tridi_to_band_bwd_ckpt_d(n, nbw, nev, Vd, td, gb, n, dv, dt, 16, w, nb) == 0
+    torch.cuda.synchronize()
+    return (zb.cpu().numpy(), gb.cpu().numpy(), dv.cpu().numpy(), dt.cpu().numpy(),
+            int(w[:4].view(torch.int32).cpu()[0]))
+
+
+# the last four run the checkpointing forward and the gradient sweep with
+# slot groups (several workgroups per column strip: enough slots per strip
+# and few strips; G = 3, 4, 4, 4)
+@pytest.mark.parametrize("n,nbw,nev", [(301, 64, 63), (150, 32, 40), (90, 8, 31), (100, 24, 17),
+                                       (1100, 64, 40), (2100, 32, 100), (700, 16, 33),
+                                       (1500, 48, 70)])
 def test_split_adjoint(oracle_mod, n, nbw, nev):
     """Checkpointing forward + backward from the checkpoints: the forward
     result is bitwise the plain forward call's, the gradients bitwise the
@@ -389,3 +417,32 @@ def test_c5_full_nev_vs_oracle(oracle_mod):
     e = (_relerr(gb[:nev, :n].T, rZ), _relerr(dv, rv), _relerr(dt, rt))
     print(f"[gpu] C5 full nev rel errors dZ {e[0]:.2e} dv {e[1]:.2e} dtau {e[2]:.2e}", flush=True)
     assert max(e) <= TOL
+
+
+def test_c5_split_pair_full_size(oracle_mod):
+    """The split pair at the benchmarked shape (n=4096, nbw=64, nev=2048:
+    128 strips, so both strip kernels run with two workgroups per strip):
+    forward result bitwise the plain forward's, gradients bitwise the
+    one-call adjoint's, and all of them against the oracle."""
+    import synth
+    n, nbw, nev = 4096, 64, 2048
+    lengths = synth.reflector_lengths(n, nbw)
+    V, tau = synth.unitary_reflectors(lengths, nbw, 1005, "d")
+    Z = synth.gaussian(n, nev, 1006, "d")
+    G = synth.gaussian(n, nev, 2005, "d")
+    print(f"[gpu] split adjoint n={n} nbw={nbw} nev={nev}", flush=True)
+    fz, gz, dv, dt, fault = _split_adjoint(Z, G, V, tau, nbw)
+    assert fault == 0
+    fwd_plain, _ = _plain_forward(Z, V, tau, nbw)
+    assert np.array_equal(fz, fwd_plain)
+    one = gpu_adjoint(Z, G, V, tau, nbw)
+    assert np.array_equal(gz, one[0][:nev, :n])
+    assert np.array_equal(dv, one[2]) and np.array_equal(dt, one[3])
+
+    def compute():
+        rZ, rv, rt = oracle_mod.adjoint(Z, G, V, tau, nbw)
+        return {"dZ": rZ, "dv": rv, "dtau": rt}
+    r = oracle_cache.cached("adjoint", dict(n=n, nbw=nbw, nev=nev, dtype="d", v_seed=1005,
+                                            z_seed=1006, g_seed=2005), compute)
+    assert _relerr(gz.T, r["dZ"]) <= TOL
+    assert _relerr(dv, r["dv"]) <= TOL and _relerr(dt, r["dtau"]) <= TOL
