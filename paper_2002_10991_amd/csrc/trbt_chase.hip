@@ -284,6 +284,9 @@ __global__ __launch_bounds__(64 * NW) void k_chase(int64_t n, int b,
     int64_t tick = 0;
 
     auto at = [&](int64_t i, int64_t k) { return bd + ((i - k) + k * LD) * E; };
+    // the same address as column base + row offset: B(i, k) is at
+    // bd + k CS + i E, and the columns a wave holds are NW apart
+    const int64_t CS = (LD - 1) * E, SNW = NW * CS;
 
     for (;;) {
         if (threadIdx.x == 0) {
@@ -291,11 +294,13 @@ __global__ __launch_bounds__(64 * NW) void k_chase(int64_t n, int b,
             s_sh = bad ? nst : (int64_t)atomicAdd(&ctl[0], 1);
         }
         __syncthreads();
-        const int64_t s = s_sh;
+        const int64_t s64 = s_sh;
         __syncthreads();   // every thread has read the ticket before the next one is taken
-        if (s >= nst) return;
-        const int64_t S = sweeps_in_stage(n, b, s);
-        const int64_t Sp = s > 0 ? sweeps_in_stage(n, b, s - 1) : 0;
+        if (s64 >= nst) return;
+        // row, column, stage and step indices fit 32 bits (n <= 2^30)
+        const int s = (int)s64, nn = (int)n;
+        const int S = (int)sweeps_in_stage(n, b, s);
+        const int Sp = s > 0 ? (int)sweeps_in_stage(n, b, s - 1) : 0;
         int64_t kref = stage_offset(n, b, s);
         // the previous step's right block, kept in registers: it is exactly
         // this step's column c and left block (rows [r0, r0+len), columns
@@ -303,34 +308,39 @@ __global__ __launch_bounds__(64 * NW) void k_chase(int64_t n, int b,
         // block), and no other step touches it in between (the one shared
         // entry, its last, was finished in the previous step's tail)
         cx car[COLS];
-        for (int64_t j = 0; j < S; ++j, ++kref) {
+        for (int j = 0; j < S; ++j, ++kref) {
             // (s-1, 0 .. j+1) done: for j > 0 the previous step's tail already
             // waited for that
             if (s > 0 && j == 0) {
                 if (threadIdx.x == 0) {
-                    fail_sh = !chase_wait(&prog[s - 1], (int)(j + 2 < Sp ? j + 2 : Sp), ctl);
+                    fail_sh = !chase_wait(&prog[s - 1], j + 2 < Sp ? j + 2 : Sp, ctl);
                 }
                 __syncthreads();
                 if (fail_sh) return;
             }
-            const int64_t r0 = s + 1 + j * b;
-            const int len = (int)(n - r0 < b ? n - r0 : b);
-            const int64_t rest = n - r0 - len;
-            const int nr = (int)(rest < b ? rest : b);          // right-block rows
-            const int64_t c = j == 0 ? s : r0 - b;
+            const int r0 = s + 1 + j * b;
+            const int len = nn - r0 < b ? nn - r0 : b;
+            const int rest = nn - r0 - len;
+            const int nr = rest < b ? rest : b;                 // right-block rows
+            const int c = j == 0 ? s : r0 - b;
             const bool has_next = j + 1 < S;                    // else the right block is stored here
             // the right block's last entry (row r0+2b-1, column r0+b-1) is
             // the leading entry of the column step (s-1, j+2) annihilates:
             // its row is finished in the tail, after that step
             const bool corner = len == b && nr == b;
             const bool crow = corner && lane == b - 1;          // this lane holds that row
+            // this wave's first block column (k = r0 + w; for the left block
+            // k = c + w) and the lane's rows (r0 + lane, r0 + len + lane)
+            double* const cw = bd + (int64_t)(r0 + w) * CS;
+            double* const cl = bd + (int64_t)(c + w) * CS;
+            const int64_t rd = (int64_t)(r0 + lane) * E, rr = (int64_t)(r0 + len + lane) * E;
 
             // 1. loads (column c + m, m = w + NW t: x for m = 0, the left
             // block for m >= 1 -- carried over for j > 0)
             cx x = {0.0, 0.0};
             if (w == 0) {
                 if (j > 0) x = car[0];
-                else if (lane < len) x = ldx_coh<C>(at(r0 + lane, c));
+                else if (lane < len) x = ldx_coh<C>(bd + (int64_t)c * CS + rd);
             }
             cx yl[COLS], yr[COLS], ad[COLS];
             // every lane issues every load (from a valid dummy address where
@@ -344,8 +354,8 @@ __global__ __launch_bounds__(64 * NW) void k_chase(int64_t n, int b,
                 // writing it now)
                 const bool okr = m < len && lane < nr && !(crow && m == b - 1);
                 const bool okd = m < len && lane >= m && lane < len;
-                yr[t] = ldx_coh<C>(okr ? at(r0 + len + lane, r0 + m) : bd);
-                ad[t] = ldx_coh<C>(okd ? at(r0 + lane, r0 + m) : bd);
+                yr[t] = ldx_coh<C>(okr ? cw + t * SNW + rr : bd);
+                ad[t] = ldx_coh<C>(okd ? cw + t * SNW + rd : bd);
             }
             // 2. the reflector (wave 0)
             if (w == 0) {
@@ -380,7 +390,7 @@ __global__ __launch_bounds__(64 * NW) void k_chase(int64_t n, int b,
                     stx<C>(ht + kref * E, tau);
                 }
                 if (lane < b) stx<C>(hv + (kref * b + lane) * E, v);
-                if (lane < len) stx_coh<C>(at(r0 + lane, c), lane == 0 ? cx{beta, 0.0} : cx{0.0, 0.0});
+                if (lane < len) stx_coh<C>(bd + (int64_t)c * CS + rd, lane == 0 ? cx{beta, 0.0} : cx{0.0, 0.0});
             }
             // the mirror of the diagonal block (its loads have been in flight
             // while wave 0 built the reflector)
@@ -413,7 +423,7 @@ __global__ __launch_bounds__(64 * NW) void k_chase(int64_t n, int b,
                     if (j > 0 && m >= 1 && m < b) {
                         const cx f = cmulc<C>(tau, dot[t]);           // conj(tau) (v^H y)
                         yl[t] = csub<C>(yl[t], cmul<C>(f, vi));
-                        if (lane < len) stx_coh<C>(at(r0 + lane, c + m), yl[t]);
+                        if (lane < len) stx_coh<C>(cl + t * SNW + rd, yl[t]);
                     }
                 }
             }
@@ -450,11 +460,11 @@ __global__ __launch_bounds__(64 * NW) void k_chase(int64_t n, int b,
                     const cx vm = ldx<C>(&vs[m * E]);
                     if (!crow) {
                         yr[t] = csub<C>(yr[t], cmul_cb<C>(tz, vm));
-                        if (!has_next && lane < nr) stx_coh<C>(at(r0 + len + lane, r0 + m), yr[t]);
+                        if (!has_next && lane < nr) stx_coh<C>(cw + t * SNW + rr, yr[t]);
                     }
                     const cx wm = shfl_x<C>(wv, m);
                     ad[t] = csub<C>(ad[t], cadd<C>(cmul_cb<C>(wv, vm), cmul_cb<C>(vi, wm)));
-                    if (lane >= m && lane < len) stx_coh<C>(at(r0 + lane, r0 + m), ad[t]);
+                    if (lane >= m && lane < len) stx_coh<C>(cw + t * SNW + rd, ad[t]);
                 }
             }
 
@@ -510,7 +520,7 @@ __global__ __launch_bounds__(64 * NW) void k_chase(int64_t n, int b,
                     const int m = w + NW * t;
                     if (m < len && crow) {
                         yr[t] = csub<C>(yr[t], cmul_cb<C>(tzc, ldx<C>(&vs[m * E])));
-                        if (!has_next) stx_coh<C>(at(r0 + len + lane, r0 + m), yr[t]);
+                        if (!has_next) stx_coh<C>(cw + t * SNW + rr, yr[t]);
                     }
                 }
             }
