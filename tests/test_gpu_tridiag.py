@@ -144,6 +144,32 @@ def test_tridiag_degenerate_clusters():
         assert np.linalg.norm(B.T @ S @ S.T @ B - np.eye(2)) <= 1e-10
 
 
+@pytest.mark.timeout(120)
+def test_tridiag_large_clusters():
+    """256 identical 2x2 blocks: two eigenvalues, each 256-fold, so the
+    orthonormalisation pass gets two clusters of 256 vectors (one workgroup
+    each).  The vectors come out orthonormal, in the right eigenspaces, and
+    the pass finishes in seconds at this n (its cost is m^2 n per cluster on
+    one workgroup)."""
+    import time
+    nb = 256
+    d = np.tile([1.0, 3.0], nb)
+    e = np.zeros(2 * nb - 1)
+    e[0::2] = 0.5                      # couple within each block only
+    n = 2 * nb
+    t0 = time.perf_counter()
+    w, Z = _gpu(d, e, n, "256 equal 2x2 blocks")
+    dt = time.perf_counter() - t0
+    lo, hi = 2.0 - np.sqrt(1.25), 2.0 + np.sqrt(1.25)   # eigenvalues of [[1, .5], [.5, 3]]
+    tn = _tnorm(d, e)
+    assert np.max(np.abs(w[:nb] - lo)) <= 1e-13 * tn and np.max(np.abs(w[nb:] - hi)) <= 1e-13 * tn
+    R = _tmul(d, e, Z) - Z * w
+    assert np.max(np.linalg.norm(R, axis=0)) <= 1e-13 * tn
+    assert np.linalg.norm(Z.T @ Z - np.eye(n)) <= 1e-12 * n
+    print(f"[gpu] two clusters of {nb}: {dt:.2f} s", flush=True)
+    assert dt < 30.0
+
+
 def test_tridiag_c2_shape_against_lapack():
     """n = 8192, lowest 4096 (the real workload's tridiagonal size): the
     tridiagonal comes from the GPU chase of that workload's band."""
