@@ -185,6 +185,34 @@ __device__ inline double row_sum(double x)
     return x;
 }
 
+// x plus x of the lane 16 apart (W = 16: rows 0/1 and 2/3) or 32 apart
+// (W = 32: the two halves), by the gfx950 lane-swap instructions (VALU, no
+// trip through the LDS crossbar).  Swapping two copies of x exchanges rows
+// 1 and 3 of the first with rows 0 and 2 of the second (W = 16), or the
+// upper half of the first with the lower half of the second (W = 32), so in
+// both lanes of a pair the first copy holds the lower lane's x and the
+// second the upper lane's: the sum is the same, in the same order, in both.
+template <int W>
+__device__ inline double swap_add(double x)
+{
+    const uint64_t u = __builtin_bit_cast(uint64_t, x);
+    const uint32_t lo = (uint32_t)u, hi = (uint32_t)(u >> 32);
+    uint32_t l0, l1, h0, h1;
+    if constexpr (W == 16) {
+        const auto l = __builtin_amdgcn_permlane16_swap(lo, lo, false, false);
+        const auto h = __builtin_amdgcn_permlane16_swap(hi, hi, false, false);
+        l0 = l[0], l1 = l[1], h0 = h[0], h1 = h[1];
+    } else {
+        static_assert(W == 32, "lane distance 16 or 32");
+        const auto l = __builtin_amdgcn_permlane32_swap(lo, lo, false, false);
+        const auto h = __builtin_amdgcn_permlane32_swap(hi, hi, false, false);
+        l0 = l[0], l1 = l[1], h0 = h[0], h1 = h[1];
+    }
+    const double a = __builtin_bit_cast(double, ((uint64_t)h0 << 32) | l0);
+    const double b = __builtin_bit_cast(double, ((uint64_t)h1 << 32) | l1);
+    return a + b;
+}
+
 // sums over the 64 lanes of N values at once (every lane gets every sum):
 // within rows by DPP, then across the four rows by two lane swaps; the N
 // values are independent and interleave
@@ -197,21 +225,20 @@ __device__ inline void wave_sums(cx (&v)[N])
         if constexpr (C) v[t].im = row_sum(v[t].im);
     }
 #pragma unroll
-    for (int off = 16; off <= 32; off <<= 1) {
+    for (int t = 0; t < N; ++t) {
+        v[t].re = swap_add<16>(v[t].re);
+        if constexpr (C) v[t].im = swap_add<16>(v[t].im);
+    }
 #pragma unroll
-        for (int t = 0; t < N; ++t) {
-            v[t].re += __shfl_xor(v[t].re, off, 64);
-            if constexpr (C) v[t].im += __shfl_xor(v[t].im, off, 64);
-        }
+    for (int t = 0; t < N; ++t) {
+        v[t].re = swap_add<32>(v[t].re);
+        if constexpr (C) v[t].im = swap_add<32>(v[t].im);
     }
 }
 
 __device__ inline double wave_sum1(double x)
 {
-    x = row_sum(x);
-    x += __shfl_xor(x, 16, 64);
-    x += __shfl_xor(x, 32, 64);
-    return x;
+    return swap_add<32>(swap_add<16>(row_sum(x)));
 }
 
 // Band copy with 2b stored diagonals (the fill of the chase), zeroed
