@@ -990,7 +990,11 @@ __global__ void k_fill_zero(double* p, int64_t count)
 // Host side
 // --------------------------------------------------------------------------
 constexpr int ADJ_WAVES = 8;     // waves (slots in flight) per strip, real
-constexpr int ADJ_WAVES_Z = 4;   // the same, complex (registers: one wave per SIMD)
+// the same, complex: two waves per SIMD, with the complex checkpointing
+// forward's registers spilling a little (140 bytes per lane at nbw = 64),
+// beats one wave per SIMD without spills (n = 4096, nev = 2048: 48.7 ->
+// 43.3 ms for forward + adjoint)
+constexpr int ADJ_WAVES_Z = 8;
 
 constexpr int ADJ_GMAX = 4;   // slot groups per strip in the split form, at most
 
