@@ -314,11 +314,13 @@ __global__ __launch_bounds__(TD_THREADS) void k_td_invit(int64_t n, int64_t nev,
 
 // Modified Gram-Schmidt over each cluster of size >= 2 (one workgroup per
 // eigenvalue index; only cluster starts with a successor in the cluster do
-// work).  Vectors in X (row-major, column j = X[r * nev + j]), already unit.
+// work).  Vectors in the output Z (column-major, vector j = Z[j * ldz ..],
+// contiguous, so the workgroup's threads read consecutive rows), already
+// unit.
 __global__ __launch_bounds__(256) void k_td_ortho(int64_t n, int64_t nev,
                                                   const double* __restrict__ w,
                                                   const double* __restrict__ bounds,
-                                                  double* __restrict__ X)
+                                                  double* __restrict__ Z, int64_t ldz)
 {
     __shared__ double red[256];
     const int64_t i = blockIdx.x;
@@ -338,17 +340,19 @@ __global__ __launch_bounds__(256) void k_td_ortho(int64_t n, int64_t nev,
         return s;
     };
     for (int64_t j = i + 1; j < nev && w[j] - w[j - 1] <= thr; ++j) {
+        double* __restrict__ zj = Z + j * ldz;
         for (int64_t m = i; m < j; ++m) {
+            const double* __restrict__ zm = Z + m * ldz;
             double p = 0.0;
-            for (int64_t r = tid; r < n; r += 256) p = fma(X[r * nev + j], X[r * nev + m], p);
+            for (int64_t r = tid; r < n; r += 256) p = fma(zj[r], zm[r], p);
             const double dt = block_sum(p);
-            for (int64_t r = tid; r < n; r += 256) X[r * nev + j] = fma(-dt, X[r * nev + m], X[r * nev + j]);
+            for (int64_t r = tid; r < n; r += 256) zj[r] = fma(-dt, zm[r], zj[r]);
             __syncthreads();
         }
         double p = 0.0;
-        for (int64_t r = tid; r < n; r += 256) p = fma(X[r * nev + j], X[r * nev + j], p);
+        for (int64_t r = tid; r < n; r += 256) p = fma(zj[r], zj[r], p);
         const double inv = 1.0 / sqrt(block_sum(p));
-        for (int64_t r = tid; r < n; r += 256) X[r * nev + j] *= inv;
+        for (int64_t r = tid; r < n; r += 256) zj[r] *= inv;
         __syncthreads();
     }
 }
@@ -439,10 +443,10 @@ int trbt_tridiag_eigh_d(int64_t n, int64_t nev, const double* d, const double* e
                        (const double*)e2, (const double*)bounds, w);
     hipLaunchKernelGGL(k_td_invit, dim3(nb), dim3(TD_THREADS), 0, st, n, nev, d, e,
                        (const double*)bounds, (const double*)w, X, F, P);
-    hipLaunchKernelGGL(k_td_ortho, dim3((unsigned)nev), dim3(256), 0, st, n, nev,
-                       (const double*)w, (const double*)bounds, X);
     hipLaunchKernelGGL(k_td_out, dim3((unsigned)((n + 31) / 32), (unsigned)((nev + 31) / 32)),
                        dim3(256), 0, st, n, nev, (const double*)X, Z, ldz);
+    hipLaunchKernelGGL(k_td_ortho, dim3((unsigned)nev), dim3(256), 0, st, n, nev,
+                       (const double*)w, (const double*)bounds, Z, ldz);
     return hipGetLastError() == hipSuccess ? TRBT_SUCCESS : TRBT_ERR_HIP;
 }
 

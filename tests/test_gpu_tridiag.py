@@ -170,6 +170,32 @@ def test_tridiag_large_clusters():
     assert dt < 30.0
 
 
+@pytest.mark.timeout(120)
+def test_tridiag_large_clusters_long_vectors():
+    """256 identical random 64x64 blocks (n = 16384): every eigenvalue is
+    256-fold, and nev = 512 takes the two lowest, two clusters of 256
+    vectors of length 16384 for the orthonormalisation pass."""
+    import time
+    rng = np.random.default_rng(31)
+    m, copies = 64, 256
+    d1, e1 = rng.standard_normal(m), rng.standard_normal(m - 1)
+    d = np.tile(d1, copies)
+    e = np.concatenate([np.concatenate([e1, [0.0]]) for _ in range(copies)])[:-1]
+    n, nev = m * copies, 512
+    t0 = time.perf_counter()
+    w, Z = _gpu(d, e, nev, "256 equal 64x64 blocks")
+    dt = time.perf_counter() - t0
+    w1 = np.linalg.eigvalsh(np.diag(d1) + np.diag(e1, 1) + np.diag(e1, -1))
+    tn = _tnorm(d, e)
+    assert np.max(np.abs(w - np.repeat(w1[:2], copies))) <= 1e-13 * tn
+    R = _tmul(d, e, Z) - Z * w
+    # the residual bound of the other checks (it grows like sqrt(n))
+    assert np.max(np.linalg.norm(R, axis=0)) <= 1e-13 * tn * max(1.0, np.sqrt(n) / 10)
+    assert np.linalg.norm(Z.T @ Z - np.eye(nev)) <= 1e-12 * nev
+    print(f"[gpu] two clusters of {copies} at n={n}: {dt:.2f} s", flush=True)
+    assert dt < 60.0
+
+
 def test_tridiag_c2_shape_against_lapack():
     """n = 8192, lowest 4096 (the real workload's tridiagonal size): the
     tridiagonal comes from the GPU chase of that workload's band."""
