@@ -33,6 +33,7 @@
 
 #include "trbt.h"
 #include "trbt_device.h"
+#include "trbt_lanes.h"
 
 namespace {
 
@@ -322,21 +323,23 @@ __global__ __launch_bounds__(256) void k_td_ortho(int64_t n, int64_t nev,
                                                   const double* __restrict__ bounds,
                                                   double* __restrict__ Z, int64_t ldz)
 {
-    __shared__ double red[256];
+    // one partial per wave, double-buffered by call parity: each thread only
+    // ever touches its own rows of Z (r = tid mod 256), so the sums are the
+    // only exchange, and one barrier per sum suffices (a wave can reach the
+    // next sum's writes only after every wave has passed this one's barrier)
+    __shared__ double red[2][4];
     const int64_t i = blockIdx.x;
     const double thr = TD_CLUSTER * bounds[2];
     if (i > 0 && w[i] - w[i - 1] <= thr) return;            // not a cluster start
     if (i + 1 >= nev || w[i + 1] - w[i] > thr) return;       // a single eigenvalue
-    const int tid = threadIdx.x;
+    const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+    int parity = 0;
     auto block_sum = [&](double v) {
-        red[tid] = v;
+        v = wave_sum(v);
+        if (lane == 0) red[parity][wv] = v;
         __syncthreads();
-        for (int h = 128; h > 0; h >>= 1) {
-            if (tid < h) red[tid] += red[tid + h];
-            __syncthreads();
-        }
-        const double s = red[0];
-        __syncthreads();
+        const double s = (red[parity][0] + red[parity][1]) + (red[parity][2] + red[parity][3]);
+        parity ^= 1;
         return s;
     };
     for (int64_t j = i + 1; j < nev && w[j] - w[j - 1] <= thr; ++j) {
@@ -347,13 +350,11 @@ __global__ __launch_bounds__(256) void k_td_ortho(int64_t n, int64_t nev,
             for (int64_t r = tid; r < n; r += 256) p = fma(zj[r], zm[r], p);
             const double dt = block_sum(p);
             for (int64_t r = tid; r < n; r += 256) zj[r] = fma(-dt, zm[r], zj[r]);
-            __syncthreads();
         }
         double p = 0.0;
         for (int64_t r = tid; r < n; r += 256) p = fma(zj[r], zj[r], p);
         const double inv = 1.0 / sqrt(block_sum(p));
         for (int64_t r = tid; r < n; r += 256) zj[r] *= inv;
-        __syncthreads();
     }
 }
 
