@@ -88,7 +88,7 @@ def test_counts_closed_form(oracle_mod, n, b):
         assert np.all(r0 + ln <= n)
 
 
-def test_counts_match_survey_table(oracle_mod):
+def test_counts_at_the_workload_shapes(oracle_mod):
     # values tabulated from the closed form for the workload shapes
     expect = {(17, 4): (36, 132), (64, 8): (272, 2008), (1024, 32): (16832, 523744),
               (4096, 64): (132992, 8386496), (8192, 64): (528128, 33550208),
