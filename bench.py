@@ -752,7 +752,7 @@ def main():
         print(json.dumps({"copy_bytes": args.copy_kernel}))
         return
     if args.gpus != 1:
-        print(f"bench.py: this build runs on one GPU only; --gpus {args.gpus} is not supported "
+        print(f"bench.py: runs on one GPU only; --gpus {args.gpus} is not supported "
               "(the back-transformation shards by eigenvector columns with no communication)",
               file=sys.stderr)
         sys.exit(2)
