@@ -157,6 +157,25 @@ def test_complex_adjoint_c5_shape_512_columns(oracle_mod):
     assert max(e) <= TOL
 
 
+@pytest.mark.timeout(900)
+def test_complex_adjoint_c5_full_nev(oracle_mod):
+    """The complex differentiation workload at its full width (n=4096,
+    nbw=64, nev=2048: 128 column strips behind grad v and grad tau, the
+    shape the benchmark times): every output against the oracle."""
+    n, nbw, nev = 4096, 64, 2048
+    Z, G, V, tau = _inputs(n, nbw, nev, 2005)
+    gZ, gv, gt = gpu_adjoint_z(Z, G, V, tau, nbw)
+
+    def compute():
+        rZ, rv, rt = oracle_mod.adjoint(Z, G, V, tau, nbw)
+        return {"dZ": rZ, "dv": rv, "dtau": rt}
+    r = oracle_cache.cached("adjoint", dict(n=n, nbw=nbw, nev=nev, dtype="z", seed=2005),
+                            compute)
+    e = (_relerr(gZ, r["dZ"]), _relerr(gv, r["dv"]), _relerr(gt, r["dtau"]))
+    print(f"[gpu] complex adjoint nev=2048 rel errors {e}", flush=True)
+    assert max(e) <= TOL
+
+
 @pytest.mark.parametrize("n,nbw,nev", [(300, 64, 40), (97, 7, 10)])
 def test_complex_adjoint_v0_not_one_nan_tail(oracle_mod, n, nbw, nev):
     """Complex v[0] != 1 (v scaled by alpha, tau by 1/|alpha|^2) and NaN beyond
