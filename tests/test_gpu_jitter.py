@@ -62,6 +62,7 @@ def test_blocked_tests_pass_under_wait_jitter():
     print("[gpu] parity / batched / adjoint tests on the wait-jitter build", flush=True)
     r = _child(["-m", "pytest", "-x", "-q", "-p", "no:cacheprovider",
                 "tests/test_gpu_parity.py::test_parity_shapes",
+                "tests/test_gpu_parity.py::test_parity_slot_groups",
                 "tests/test_gpu_batched.py::test_batched_mixed_two_replays",
                 "tests/test_gpu_batched.py::test_batched_equals_looped_bitwise",
                 "tests/test_gpu_adjoint.py::test_adjoint_vs_oracle",
