@@ -234,6 +234,33 @@ int trans_ev_tridi_to_band_adjoint_z(int64_t n, int nbw, int64_t nev,
                                      trbt_z *dv, trbt_z *dtau, int ckpt_every,
                                      void *work, size_t work_bytes, void *stream);
 
+/* The complex adjoint in two halves, like the real pair above (the same
+ * reverse-mode definition, conjugate-Wirtinger gradients), for nbw in
+ * {16, 32, 48, 64}:
+ *   trans_ev_tridi_to_band_fwd_ckpt_z  Z <- Q^* Z in place (bitwise the
+ *       result of trans_ev_tridi_to_band_z) and the checkpoints into `work`.
+ *       Arguments: 1 n, 2 nbw, 3 nev, 4 hh_v, 5 hh_tau, 6 Z, 7 ldz,
+ *       8 ckpt_every (0 or 16), 9 work, 10 work_bytes, 11 stream.
+ *   trans_ev_tridi_to_band_bwd_ckpt_z  G <- grad Z_in and dv, dtau (bitwise
+ *       those of trans_ev_tridi_to_band_adjoint_z) from the checkpoints a
+ *       previous fwd_ckpt_z call with the same n, nbw, nev and reflectors
+ *       left in `work` (ordered before it on the stream; work untouched in
+ *       between).  Arguments: 1 n, 2 nbw, 3 nev, 4 hh_v, 5 hh_tau, 6 G,
+ *       7 ldg, 8 dv, 9 dtau, 10 ckpt_every, 11 work, 12 work_bytes, 13 stream.
+ * Complex hh_v, hh_tau, Z, G, dv, dtau; ldz, ldg in complex elements;
+ * workspace size: trbt_adjoint_workspace_bytes_z.  Status codes as the real
+ * pair, and -2 for any other nbw (those band widths have only the one-call
+ * complex adjoint), -1 also for n beyond the blocked kernels' range. */
+int trans_ev_tridi_to_band_fwd_ckpt_z(int64_t n, int nbw, int64_t nev,
+                                      const trbt_z *hh_v, const trbt_z *hh_tau,
+                                      trbt_z *Z, int64_t ldz, int ckpt_every,
+                                      void *work, size_t work_bytes, void *stream);
+int trans_ev_tridi_to_band_bwd_ckpt_z(int64_t n, int nbw, int64_t nev,
+                                      const trbt_z *hh_v, const trbt_z *hh_tau,
+                                      trbt_z *G, int64_t ldg, trbt_z *dv, trbt_z *dtau,
+                                      int ckpt_every, void *work, size_t work_bytes,
+                                      void *stream);
+
 /* ------------------------------------------------------------------------
  * Batched back-transformation: many independent problems of uneven size
  * (k-points, spin channels), all real or all complex, each exactly the

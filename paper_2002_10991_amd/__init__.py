@@ -27,6 +27,7 @@ __all__ = [
     "trans_ev_tridi_to_band_bwd_ckpt_d", "adjoint", "BackTransform", "back_transform_autograd",
     "trbt_band_to_tridi_workspace_bytes", "trbt_band_to_tridi_d", "trbt_band_to_tridi_z",
     "trbt_adjoint_workspace_bytes_z", "trans_ev_tridi_to_band_adjoint_z",
+    "trans_ev_tridi_to_band_fwd_ckpt_z", "trans_ev_tridi_to_band_bwd_ckpt_z",
     "band_to_tridiagonal", "trbt_tridiag_eigh_workspace_bytes", "trbt_tridiag_eigh_d",
     "tridiagonal_eigh", "trbt_work_check", "trbt_band_to_full_workspace_bytes",
     "trans_ev_band_to_full_d", "trans_ev_band_to_full_z", "band_to_full",
@@ -101,6 +102,12 @@ def lib():
         L.trans_ev_tridi_to_band_adjoint_z.argtypes = \
             L.trans_ev_tridi_to_band_adjoint_d.argtypes
         L.trans_ev_tridi_to_band_adjoint_z.restype = i32
+        L.trans_ev_tridi_to_band_fwd_ckpt_z.argtypes = \
+            L.trans_ev_tridi_to_band_fwd_ckpt_d.argtypes
+        L.trans_ev_tridi_to_band_fwd_ckpt_z.restype = i32
+        L.trans_ev_tridi_to_band_bwd_ckpt_z.argtypes = \
+            L.trans_ev_tridi_to_band_bwd_ckpt_d.argtypes
+        L.trans_ev_tridi_to_band_bwd_ckpt_z.restype = i32
         L.trbt_tridiag_eigh_workspace_bytes.argtypes = [i64, i64, C.POINTER(sz)]
         L.trbt_tridiag_eigh_workspace_bytes.restype = i32
         L.trbt_tridiag_eigh_d.argtypes = [i64, i64, vp, vp, vp, vp, i64, vp, sz, vp]
@@ -429,6 +436,20 @@ def trans_ev_tridi_to_band_bwd_ckpt_d(n, nbw, nev, hh_v, hh_tau, G, ldg, dv, dta
         _ptr(work), work_bytes, _stream(stream))
 
 
+def trans_ev_tridi_to_band_fwd_ckpt_z(n, nbw, nev, hh_v, hh_tau, Z, ldz, ckpt_every, work,
+                                      work_bytes, stream=None) -> int:
+    return lib().trans_ev_tridi_to_band_fwd_ckpt_z(
+        n, nbw, nev, _ptr(hh_v), _ptr(hh_tau), _ptr(Z), ldz, ckpt_every, _ptr(work), work_bytes,
+        _stream(stream))
+
+
+def trans_ev_tridi_to_band_bwd_ckpt_z(n, nbw, nev, hh_v, hh_tau, G, ldg, dv, dtau, ckpt_every,
+                                      work, work_bytes, stream=None) -> int:
+    return lib().trans_ev_tridi_to_band_bwd_ckpt_z(
+        n, nbw, nev, _ptr(hh_v), _ptr(hh_tau), _ptr(G), ldg, _ptr(dv), _ptr(dtau), ckpt_every,
+        _ptr(work), work_bytes, _stream(stream))
+
+
 def _adjoint_workspace(n, nbw, nev, device, cplx=False):
     import torch
     nb = (trbt_adjoint_workspace_bytes_z if cplx else trbt_adjoint_workspace_bytes_d)(n, nbw, nev)
@@ -487,13 +508,15 @@ def _back_transform_function():
     class BackTransform(torch.autograd.Function):
         """Z_out = H_0 ... H_{K-1} Z_in with the hand-written adjoint.
 
-        Real: the forward pass runs the checkpointing forward kernel and
-        keeps its workspace (a checkpoint every 16 stages, not the states in
-        between) for the backward pass, which recomputes the states inside
-        each 16-stage block from it.  Complex: the forward pass is the plain
-        transformation; the backward pass runs the one-call complex adjoint
-        from the saved Z_in (conjugate-Wirtinger gradients, as PyTorch's
-        complex autograd expects)."""
+        The forward pass runs the checkpointing forward kernel and keeps its
+        workspace (a checkpoint every 16 stages, not the states in between)
+        for the backward pass, which recomputes the states inside each
+        16-stage block from it; the backward pass only reads the
+        checkpoints, so it may run more than once (retain_graph).  Complex (conjugate-Wirtinger gradients, as
+        PyTorch's complex autograd expects) takes the same split pair for
+        nbw in {16, 32, 48, 64}; for other band widths the forward pass is
+        the plain transformation and the backward pass the one-call complex
+        adjoint from the saved Z_in."""
 
         @staticmethod
         def forward(ctx, Z_in, hh_v, hh_tau, nbw):
@@ -502,9 +525,21 @@ def _back_transform_function():
             v = hh_v.detach().contiguous()
             t = hh_tau.detach().contiguous()
             if out.dtype == torch.complex128 and v.dtype == out.dtype and t.dtype == out.dtype:
+                ctx.cplx, ctx.nbw, ctx.shape = True, nbw, (n, nev)
+                if nbw in (16, 32, 48, 64):
+                    work, nb = _adjoint_workspace(n, nbw, nev, out.device, True)
+                    rc = trans_ev_tridi_to_band_fwd_ckpt_z(n, nbw, nev, v, t, out, max(n, 1), 16,
+                                                           work, nb)
+                    if rc == 0:
+                        ctx.split = True
+                        ctx.save_for_backward(v, t)
+                        ctx.work, ctx.nb = work, nb
+                        return out
+                    if rc != -1:   # -1 (n beyond the blocked kernels' range): nothing ran
+                        raise TrbtError(rc, "trans_ev_tridi_to_band_fwd_ckpt_z")
+                ctx.split = False
                 back_transform(out, v, t, nbw)
                 ctx.save_for_backward(v, t, Z_in.detach().clone())
-                ctx.cplx, ctx.nbw, ctx.shape = True, nbw, (n, nev)
                 return out
             if v.dtype != torch.float64 or out.dtype != torch.float64 or t.dtype != torch.float64:
                 raise TypeError("the differentiable back-transformation takes float64 or "
@@ -521,6 +556,19 @@ def _back_transform_function():
 
         @staticmethod
         def backward(ctx, grad_out):
+            if ctx.cplx and ctx.split:
+                v, t = ctx.saved_tensors
+                n, nev = ctx.shape
+                gbuf, g = _colmajor(grad_out.to(torch.complex128))
+                K = v.shape[0]
+                dv = torch.empty(max(K, 1), ctx.nbw, dtype=torch.complex128, device=v.device)[:K]
+                dt = torch.empty(max(K, 1), dtype=torch.complex128, device=v.device)[:K]
+                rc = trans_ev_tridi_to_band_bwd_ckpt_z(n, ctx.nbw, nev, v, t, g, max(n, 1),
+                                                       dv if K else None, dt if K else None, 16,
+                                                       ctx.work, ctx.nb)
+                if rc:
+                    raise TrbtError(rc, "trans_ev_tridi_to_band_bwd_ckpt_z")
+                return g, dv, dt, None
             if ctx.cplx:
                 v, t, zin = ctx.saved_tensors
                 _, zc = _colmajor(zin)
@@ -538,7 +586,6 @@ def _back_transform_function():
                                                    ctx.work, ctx.nb)
             if rc:
                 raise TrbtError(rc, "trans_ev_tridi_to_band_bwd_ckpt_d")
-            ctx.work = None
             return g, dv, dt, None
 
     return BackTransform

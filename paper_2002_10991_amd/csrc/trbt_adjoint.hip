@@ -1157,35 +1157,36 @@ int launch_strips(K1 kern1, KG kernG, int64_t ns, int64_t J, int nw, int* gprog,
 
 // The adjoint in two halves.  adj_forward: the forward transformation of Z
 // (in place) that also writes the checkpoints into the workspace;
-// adj_backward: the reverse sweep from those checkpoints.
-template <int NB>
+// adj_backward: the reverse sweep from those checkpoints.  Real or complex
+// (interleaved re, im; ldz, ldg in elements).
+template <int NB, bool CPLX = false>
 void blocked_forward(int64_t n, int64_t nev, const double* hv, const double* ht, double* Z,
                      int64_t ldz, char* ws, const AdjLayout& L, hipStream_t st)
 {
+    constexpr int NW = CPLX ? ADJ_WAVES_Z : ADJ_WAVES;
     double* fwd = (double*)(ws + L.fwd);
     const unsigned nb = (unsigned)L.nblocks;
-    hipLaunchKernelGGL((k_pack<NB, false, rotating_window<NB, false>()>), dim3(nb), dim3(256), 0,
+    hipLaunchKernelGGL((k_pack<NB, CPLX, rotating_window<NB, CPLX>()>), dim3(nb), dim3(256), 0,
                        st, n, hv, ht, fwd);
-    launch_strips(k_blocked_ckpt<NB, ADJ_WAVES, false, false>,
-                  k_blocked_ckpt<NB, ADJ_WAVES, false, true>, L.nstrips,
-                  sweeps_in_stage(n, NB, 0), ADJ_WAVES, (int*)(ws + L.gprog), st, n, nev,
+    launch_strips(k_blocked_ckpt<NB, NW, CPLX, false>, k_blocked_ckpt<NB, NW, CPLX, true>,
+                  L.nstrips, sweeps_in_stage(n, NB, 0), NW, (int*)(ws + L.gprog), st, n, nev,
                   (const double*)fwd, Z, ldz, (double*)(ws + L.ckpt), (unsigned*)ws);
 }
 
-template <int NB>
+template <int NB, bool CPLX = false>
 void blocked_backward(int64_t n, int64_t nev, const double* hv, const double* ht, double* G,
                       int64_t ldg, double* dv, double* dtau, char* ws, const AdjLayout& L,
                       hipStream_t st)
 {
+    constexpr int NW = CPLX ? ADJ_WAVES_Z : ADJ_WAVES;
     double* apk = (double*)(ws + L.apk);
     double* gck = (double*)(ws + L.gck);
     const unsigned nb = (unsigned)L.nblocks, ns = (unsigned)L.nstrips;
-    hipLaunchKernelGGL((k_pack_adj<NB, false>), dim3(nb), dim3(256), 0, st, n, hv, ht, apk);
-    launch_strips(k_adj_sweep<NB, ADJ_WAVES, false, false>,
-                  k_adj_sweep<NB, ADJ_WAVES, false, true>, L.nstrips, sweeps_in_stage(n, NB, 0),
-                  ADJ_WAVES, (int*)(ws + L.gprog), st, n, nev, (const double*)apk, G, ldg, gck,
-                  (unsigned*)ws);
-    hipLaunchKernelGGL((k_adj_reduce<NB, 4, false>), dim3(nb), dim3(256), 0, st, n, (int64_t)ns,
+    hipLaunchKernelGGL((k_pack_adj<NB, CPLX>), dim3(nb), dim3(256), 0, st, n, hv, ht, apk);
+    launch_strips(k_adj_sweep<NB, NW, CPLX, false>, k_adj_sweep<NB, NW, CPLX, true>, L.nstrips,
+                  sweeps_in_stage(n, NB, 0), NW, (int*)(ws + L.gprog), st, n, nev,
+                  (const double*)apk, G, ldg, gck, (unsigned*)ws);
+    hipLaunchKernelGGL((k_adj_reduce<NB, 4, CPLX>), dim3(nb), dim3(256), 0, st, n, (int64_t)ns,
                        (const double*)apk, (const double*)(ws + L.ckpt), (const double*)gck, dv,
                        dtau);
 }
@@ -1404,6 +1405,83 @@ int trans_ev_tridi_to_band_bwd_ckpt_d(int64_t n, int nbw, int64_t nev, const dou
     const AdjLayout L = adj_layout(n, nbw, nev);
     if (!work || work_bytes < L.total) return TRBT_ERR_WORKSPACE;
     return adj_backward(n, nbw, nev, hh_v, hh_tau, G, ldg, dv, dtau, (char*)work, L, st);
+}
+
+int trans_ev_tridi_to_band_fwd_ckpt_z(int64_t n, int nbw, int64_t nev, const trbt_z* hh_v,
+                                      const trbt_z* hh_tau, trbt_z* Z, int64_t ldz,
+                                      int ckpt_every, void* work, size_t work_bytes, void* stream)
+{
+    if (n < 0) return -1;
+    if (!blocked_eligible(nbw)) return -2;
+    if (nev < 0 || nev > n) return -3;
+    const int64_t K = num_reflectors(n, nbw);
+    const bool active = K > 0 && nev > 0;
+    if (active && !hh_v) return -4;
+    if (active && !hh_tau) return -5;
+    if (active && !Z) return -6;
+    if (ldz < (n > 1 ? n : 1)) return -7;
+    if (ckpt_every != 0 && ckpt_every != 16) return -8;
+    if (work && ((uintptr_t)work % TRBT_WORK_ALIGN)) return -9;
+    if (work_bytes && !work) return -9;
+    if (active && !use_blocked(n, nbw, true)) return -1;   // beyond the blocked kernels' range
+    if (!active) return TRBT_SUCCESS;
+    int rc = check_device();
+    if (rc) return rc;
+    const AdjLayout L = adj_layout(n, nbw, nev, true);
+    if (!work || work_bytes < L.total) return TRBT_ERR_WORKSPACE;
+    hipStream_t st = (hipStream_t)stream;
+    hipLaunchKernelGGL(k_zero_words, dim3(1), dim3(64), 0, st, (unsigned*)work, 64);
+    const double *hv = (const double*)hh_v, *ht = (const double*)hh_tau;
+    double* Zd = (double*)Z;
+    char* ws = (char*)work;
+    switch (nbw) {
+        case 16: blocked_forward<16, true>(n, nev, hv, ht, Zd, ldz, ws, L, st); break;
+        case 32: blocked_forward<32, true>(n, nev, hv, ht, Zd, ldz, ws, L, st); break;
+        case 48: blocked_forward<48, true>(n, nev, hv, ht, Zd, ldz, ws, L, st); break;
+        case 64: blocked_forward<64, true>(n, nev, hv, ht, Zd, ldz, ws, L, st); break;
+        default: return TRBT_ERR_INTERNAL;
+    }
+    return hipGetLastError() == hipSuccess ? TRBT_SUCCESS : TRBT_ERR_HIP;
+}
+
+int trans_ev_tridi_to_band_bwd_ckpt_z(int64_t n, int nbw, int64_t nev, const trbt_z* hh_v,
+                                      const trbt_z* hh_tau, trbt_z* G, int64_t ldg, trbt_z* dv,
+                                      trbt_z* dtau, int ckpt_every, void* work,
+                                      size_t work_bytes, void* stream)
+{
+    if (n < 0) return -1;
+    if (!blocked_eligible(nbw)) return -2;
+    if (nev < 0 || nev > n) return -3;
+    const int64_t K = num_reflectors(n, nbw);
+    if (K > 0 && !hh_v) return -4;
+    if (K > 0 && !hh_tau) return -5;
+    if (K > 0 && nev > 0 && !G) return -6;
+    if (ldg < (n > 1 ? n : 1)) return -7;
+    if (K > 0 && !dv) return -8;
+    if (K > 0 && !dtau) return -9;
+    if (ckpt_every != 0 && ckpt_every != 16) return -10;
+    if (work && ((uintptr_t)work % TRBT_WORK_ALIGN)) return -11;
+    if (work_bytes && !work) return -11;
+    if (K > 0 && nev > 0 && !use_blocked(n, nbw, true)) return -1;
+    if (K == 0) return TRBT_SUCCESS;
+    int rc = check_device();
+    if (rc) return rc;
+    hipStream_t st = (hipStream_t)stream;
+    // complex dv (K x nbw) and dtau (K): twice the doubles of the real ones
+    if (nev == 0) return zero_grads(2 * K, nbw, (double*)dv, (double*)dtau, st);
+    const AdjLayout L = adj_layout(n, nbw, nev, true);
+    if (!work || work_bytes < L.total) return TRBT_ERR_WORKSPACE;
+    const double *hv = (const double*)hh_v, *ht = (const double*)hh_tau;
+    double *Gd = (double*)G, *dvd = (double*)dv, *dtd = (double*)dtau;
+    char* ws = (char*)work;
+    switch (nbw) {
+        case 16: blocked_backward<16, true>(n, nev, hv, ht, Gd, ldg, dvd, dtd, ws, L, st); break;
+        case 32: blocked_backward<32, true>(n, nev, hv, ht, Gd, ldg, dvd, dtd, ws, L, st); break;
+        case 48: blocked_backward<48, true>(n, nev, hv, ht, Gd, ldg, dvd, dtd, ws, L, st); break;
+        case 64: blocked_backward<64, true>(n, nev, hv, ht, Gd, ldg, dvd, dtd, ws, L, st); break;
+        default: return TRBT_ERR_INTERNAL;
+    }
+    return hipGetLastError() == hipSuccess ? TRBT_SUCCESS : TRBT_ERR_HIP;
 }
 
 }  // extern "C"

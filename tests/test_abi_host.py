@@ -267,6 +267,52 @@ def test_split_adjoint_validation_codes(T):
     assert callb(nbw=1, hv=None, ht=None, dv=None, dt=None) == 0
 
 
+def test_complex_split_adjoint_validation_codes(T):
+    """The complex pair validates like the real one, and rejects band widths
+    without blocked kernels with -2, all before any HIP call."""
+    fw = T.trans_ev_tridi_to_band_fwd_ckpt_z
+    okf = dict(n=100, nbw=32, nev=10, hv=FAKE, ht=FAKE, Z=FAKE, ldz=100, ck=16, work=None, wb=0)
+
+    def callf(**kw):
+        a = dict(okf, **kw)
+        return fw(a["n"], a["nbw"], a["nev"], a["hv"], a["ht"], a["Z"], a["ldz"], a["ck"],
+                  a["work"], a["wb"], 0)
+
+    assert callf(n=-1) == -1
+    for nbw in (0, 8, 24, 80, 128, 300):
+        assert callf(nbw=nbw) == -2
+    assert callf(nev=-2) == -3
+    assert callf(hv=None) == -4
+    assert callf(ht=None) == -5
+    assert callf(Z=None) == -6
+    assert callf(ldz=10) == -7
+    assert callf(ck=32) == -8
+    assert callf(work=FAKE + 4) == -9
+    assert callf(nev=0, hv=None, ht=None, Z=None) == 0
+    bw = T.trans_ev_tridi_to_band_bwd_ckpt_z
+    okb = dict(n=100, nbw=32, nev=10, hv=FAKE, ht=FAKE, G=FAKE, ldg=100, dv=FAKE, dt=FAKE, ck=16,
+               work=None, wb=0)
+
+    def callb(**kw):
+        a = dict(okb, **kw)
+        return bw(a["n"], a["nbw"], a["nev"], a["hv"], a["ht"], a["G"], a["ldg"], a["dv"],
+                  a["dt"], a["ck"], a["work"], a["wb"], 0)
+
+    assert callb(n=-1) == -1
+    for nbw in (0, 1, 8, 96):
+        assert callb(nbw=nbw) == -2
+    assert callb(nev=101) == -3
+    assert callb(hv=None) == -4
+    assert callb(ht=None) == -5
+    assert callb(G=None) == -6
+    assert callb(ldg=99) == -7
+    assert callb(dv=None) == -8
+    assert callb(dt=None) == -9
+    assert callb(ck=1) == -10
+    assert callb(work=None, wb=8) == -11
+    assert callb(n=2, hv=None, ht=None, dv=None, dt=None, G=None, ldg=2, nev=1) == 0
+
+
 @pytest.mark.parametrize("fn", ["trbt_band_to_tridi_d", "trbt_band_to_tridi_z"])
 def test_band_to_tridi_validation_codes(T, fn):
     f = getattr(T, fn)

@@ -102,6 +102,77 @@ def test_complex_adjoint_degenerate(oracle_mod):
     assert np.array_equal(g.cpu().numpy(), G) and dv.numel() == 0
 
 
+def _split_pair_z(Z, G, V, tau, nbw):
+    """The complex split pair on device copies: (forward result, grad Z_in,
+    dv, dtau, status of the two calls)."""
+    import torch
+    import paper_2002_10991_amd as T
+    n, nev = Z.shape
+    Vd = torch.from_numpy(V).to("cuda")
+    td = torch.from_numpy(tau).to("cuda")
+    zb = torch.from_numpy(np.ascontiguousarray(Z.T)).to("cuda")
+    gb = torch.from_numpy(np.ascontiguousarray(G.T)).to("cuda")
+    K = len(tau)
+    dv = torch.empty(K, nbw, dtype=torch.complex128, device="cuda")
+    dt = torch.empty(K, dtype=torch.complex128, device="cuda")
+    nb = T.trbt_adjoint_workspace_bytes_z(n, nbw, nev)
+    w = torch.empty(nb + 256, dtype=torch.uint8, device="cuda")
+    w = w[(-w.data_ptr()) % 256:][:nb]
+    r1 = T.trans_ev_tridi_to_band_fwd_ckpt_z(n, nbw, nev, Vd, td, zb, n, 16, w, nb)
+    r2 = T.trans_ev_tridi_to_band_bwd_ckpt_z(n, nbw, nev, Vd, td, gb, n, dv, dt, 16, w, nb)
+    torch.cuda.synchronize()
+    if (r1, r2) == (0, 0):
+        assert T.trbt_work_check(w) == 0
+    return zb.cpu().numpy(), gb.cpu().numpy(), dv.cpu().numpy(), dt.cpu().numpy(), (r1, r2)
+
+
+# the last three run the checkpointing forward and the sweep with slot
+# groups (enough slots per strip, few strips)
+@pytest.mark.parametrize("n,nbw,nev", [(301, 64, 63), (150, 32, 40), (200, 48, 17),
+                                       (100, 16, 33), (1100, 64, 40), (700, 16, 33),
+                                       (1500, 48, 70)])
+def test_complex_split_pair(oracle_mod, n, nbw, nev):
+    """trans_ev_tridi_to_band_{fwd,bwd}_ckpt_z: the forward result bitwise
+    the plain complex forward's, the gradients bitwise the one-call complex
+    adjoint's, and both against the oracle."""
+    import torch
+    import paper_2002_10991_amd as T
+    Z, G, V, tau = _inputs(n, nbw, nev, 640 + n + nbw)
+    print(f"[gpu] complex split pair n={n} nbw={nbw} nev={nev}", flush=True)
+    fz, gz, dv, dt, rcs = _split_pair_z(Z, G, V, tau, nbw)
+    assert rcs == (0, 0)
+    zb = torch.from_numpy(np.ascontiguousarray(Z.T)).to("cuda")
+    T.back_transform(zb.T, torch.from_numpy(V).to("cuda"), torch.from_numpy(tau).to("cuda"), nbw)
+    torch.cuda.synchronize()
+    assert np.array_equal(fz, zb.cpu().numpy())
+    oZ, ov, ot = gpu_adjoint_z(Z, G, V, tau, nbw)
+    assert np.array_equal(gz.T, oZ) and np.array_equal(dv, ov) and np.array_equal(dt, ot)
+    rZ, rv, rt = oracle_mod.adjoint(Z, G, V, tau, nbw)
+    assert _relerr(gz.T, rZ) <= TOL and _relerr(dv, rv) <= TOL and _relerr(dt, rt) <= TOL
+
+
+def test_complex_split_pair_other_band_widths():
+    """Band widths without blocked kernels: status -2 from both halves
+    (before any launch); the autograd wrapper then takes the one-call
+    adjoint."""
+    Z, G, V, tau = _inputs(90, 8, 10, 5)
+    *_, rcs = _split_pair_z(Z, G, V, tau, 8)
+    assert rcs == (-2, -2)
+
+
+def test_complex_autograd_gradcheck_blocked():
+    """gradcheck through the split pair (nbw = 16)."""
+    import torch
+    import paper_2002_10991_amd as T
+    n, nbw, nev = 36, 16, 2
+    Z, _, V, tau = _inputs(n, nbw, nev, 78, general_tau=True)
+    print(f"[gpu] gradcheck complex n={n} nbw={nbw} nev={nev}", flush=True)
+    args = [torch.from_numpy(np.ascontiguousarray(a)).to("cuda").requires_grad_(True)
+            for a in (Z, V, tau)]
+    assert torch.autograd.gradcheck(lambda z, v, t: T.back_transform_autograd(z, v, t, nbw),
+                                    args, eps=1e-6, atol=1e-7, rtol=1e-6)
+
+
 def test_complex_autograd_gradcheck():
     import torch
     import paper_2002_10991_amd as T
